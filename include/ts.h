@@ -1,0 +1,192 @@
+/*
+ * ts.h -- C ABI of the MI355X (gfx950) triangle-splatting rasterizer.
+ *
+ * The library renders a soup of independent 3D triangles into an image and
+ * back-propagates through it, as in "Triangle Splatting for Real-Time
+ * Radiance Field Rendering" (arXiv 2505.19175):
+ *   - each triangle has three vertices v_i, an opacity o, a smoothness sigma
+ *     and spherical-harmonic colour coefficients                  (Sec. 3.1)
+ *   - vertices are projected with a pinhole camera q = K(R v + t)  (Sec. 3.1)
+ *   - each pixel p weighs a triangle by the window
+ *     I(p) = ReLU(phi(p)/phi(s))^sigma, phi the 2D signed distance to the
+ *     triangle and s its incentre                                  (Eq. 1)
+ *   - colours are blended front to back in depth order with o*I as opacity
+ *     (Sec. 3.1; the blending weight T*o of Sec. 3.2)
+ *   - triangles are assigned to 16x16 pixel tiles through a tight box that
+ *     drops the rim where o*I < tau_cutoff                         (Supp., "Tile assignment")
+ *   - the depth order is that of the triangle centres             (Supp., "Depth sorting")
+ *   - SH colour up to degree 3, 59 parameters per triangle        (Sec. 4, "Implementation details")
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - camera: x_c = R v + t with OpenCV axes (x right, y down, z forward);
+ *     q = (fx x_c/z_c + cx, fy y_c/z_c + cy); pixel (i,j) is sampled at its
+ *     centre (i+1/2, j+1/2)
+ *   - a triangle is dropped if any vertex has z_c <= z_near, if its 2D
+ *     inradius is below r_min, if o < alpha_min, or if its tight box holds
+ *     no pixel centre; no back-face culling
+ *   - alpha = min(alpha_max, o*I); a fragment with alpha < alpha_min is
+ *     skipped; one whose T(1-alpha) would fall below T_min ends the pixel
+ *   - depth key = float32 of the mean camera-space z of the three vertices,
+ *     ties broken by triangle index
+ *   - colour = max(0, sum_k sh_k Y_k(d) + 1/2), d the unit direction from
+ *     the camera centre to the triangle centroid, Y_k the real orthonormal
+ *     SH basis with index l*l+l+m and no Condon-Shortley phase
+ *   - outputs: rgb = sum w c + bg T_final, alpha = 1 - T_final,
+ *     depth = sum w z (not normalised)
+ *
+ * Memory: every pointer argument except the ts_camera / ts_config structs
+ * and h_count is a DEVICE pointer owned by the caller; the library never
+ * allocates or frees.  Buffers are row-major and contiguous; images are
+ * planar [C][H][W] float32.  All calls are asynchronous on `stream`; only
+ * ts_bin_sort with a non-NULL h_count synchronises it.
+ *
+ * Errors: every entry point returns TS_OK (0) or a TS_E* code and launches
+ * nothing on a validation error.  TS_EHIP wraps a failed HIP launch (the HIP
+ * error string is available from ts_last_error()).  Inputs are not checked
+ * for NaN/Inf.
+ */
+#ifndef TS_H
+#define TS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TS_OK 0
+#define TS_EINVAL 1      /* null pointer, negative size, bad degree, image too large */
+#define TS_ECAPACITY 2   /* instance count exceeds ts_bins.capacity */
+#define TS_EWORKSPACE 3  /* workspace smaller than the size query */
+#define TS_EHIP 4        /* a HIP call failed */
+
+#define TS_TILE 16               /* tile edge in pixels */
+#define TS_G2D_STRIDE 16         /* floats per triangle in ts_proj.g2d */
+#define TS_MAX_SH_DEGREE 3
+#define TS_MAX_IMAGE_DIM 16384   /* width and height limit (int16 pixel rects) */
+
+/* Pinhole camera (Sec. 3.1): world -> camera x_c = R v + t, R row-major. */
+typedef struct ts_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} ts_camera;
+
+/* Rasterizer constants: alpha_min is the paper's tau_cutoff. */
+typedef struct ts_config {
+    float alpha_min;   /* cut-off: fragments with alpha < alpha_min are skipped (1/255) */
+    float alpha_max;   /* opacity clamp (0.99) */
+    float T_min;       /* early-termination transmittance (1e-4) */
+    float z_near;      /* near plane (0.2) */
+    float r_min;       /* smallest 2D inradius kept, pixels (1e-6) */
+    int32_t sh_degree; /* 0..3 */
+    float bg[3];       /* background colour */
+} ts_config;
+
+/* Per-view projection state, N entries each, allocated by the caller.
+ * Written by ts_project, read by ts_bin_sort and the renderers. */
+typedef struct ts_proj {
+    void* rec;          /* [N] raster records, ts_proj_record_bytes() each, 16-byte aligned */
+    int16_t* rect;      /* [N][4] tight pixel box px0, px1, py0, py1 (px0 > px1: empty) */
+    float* depth;       /* [N] depth key */
+    uint32_t* ntiles;   /* [N] tiles covered; 0 = culled */
+    float* g2d;         /* [N][TS_G2D_STRIDE] per-triangle 2D gradient accumulators;
+                           zeroed by ts_project for visible triangles, consumed (and
+                           re-zeroed) by ts_render_backward */
+} ts_proj;
+
+/* Tile lists of one view.  keys/vals/ranges are outputs of ts_bin_sort. */
+typedef struct ts_bins {
+    uint64_t* keys;     /* [capacity] (tile << 32) | depth bits, sorted; may be NULL */
+    uint32_t* vals;     /* [capacity] triangle index of each instance, sorted */
+    uint32_t* ranges;   /* [tiles][2] [start, end) of each tile in vals; (0,0) if empty */
+    uint32_t* d_count;  /* [4] device counters: [0] instances M, [1] visible N_v,
+                           [2] overflow flag (M > capacity), [3] reserved */
+    uint64_t capacity;  /* entries available in keys / vals */
+} ts_bins;
+
+/* Bytes of one raster record (the layout is private to the library). */
+size_t ts_proj_record_bytes(void);
+
+/* Tiles of a width x height image: ceil(W/16) * ceil(H/16). */
+int32_t ts_num_tiles(int32_t width, int32_t height);
+
+/* Workspace bytes ts_bin_sort needs for N triangles, `capacity` instances
+ * and `num_tiles` tiles. */
+size_t ts_bin_sort_workspace_bytes(int64_t N, uint64_t capacity, int32_t num_tiles);
+
+/*
+ * Projection, culling, window set-up and SH colour (Sec. 3.1; Supp. "Tile
+ * assignment"), one thread per triangle, set-up in FP64.
+ *   v      [N][3][3] vertices (world)        o     [N] opacity in (0,1]
+ *   sigma  [N] window smoothness > 0         sh    [N][(deg+1)^2][3] SH coefficients
+ * Writes every field of *out for all N triangles (records only for visible
+ * ones).  N = 0 is valid and launches nothing.
+ */
+int ts_project(const float* v, const float* o, const float* sigma, const float* sh, int64_t N,
+               const ts_camera* cam, const ts_config* cfg, const ts_proj* out,
+               hipStream_t stream);
+
+/*
+ * Tile binning and depth ordering (Supp. "Tile assignment", "Depth
+ * sorting"): each visible triangle emits one instance per 16x16 tile of its
+ * tight box; instances are stably ordered by (tile, depth key, triangle
+ * index) and ranges[t] gives tile t's run.  Device radix sorts, no host
+ * round trip unless h_count is non-NULL.
+ *   ws/ws_bytes  workspace of ts_bin_sort_workspace_bytes(N, capacity, tiles)
+ *   h_count      optional host uint32_t[2]: receives (M, N_v); the call then
+ *                synchronises `stream` and sizes later launches exactly.
+ *                With h_count == NULL the launches are sized by N and
+ *                capacity and read M from out->d_count on the device.
+ * Returns TS_ECAPACITY when M > capacity and h_count is non-NULL (M is left
+ * in h_count[0] and d_count[0]); with h_count == NULL an overflow sets
+ * d_count[2] and the lists hold only the first `capacity` instances.
+ */
+int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, size_t ws_bytes,
+                const ts_bins* out, uint32_t* h_count, hipStream_t stream);
+
+/*
+ * Forward compositing (Eq. 1; Sec. 3.1): one 256-thread workgroup per tile,
+ * records staged through LDS, per-pixel FP64 edge functions and FP32
+ * blending, wavefront-ballot early termination.
+ * Outputs (device, [H][W] unless noted): rgb [3][H][W], alpha, depth,
+ * T_final (transmittance left), last (number of list entries of the pixel's
+ * tile up to and including its last composited fragment; backward state).
+ */
+int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                      const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                      float* T_final, uint32_t* last, hipStream_t stream);
+
+/*
+ * Backward pass (end-to-end gradients, Sec. 3.3): reverse traversal of each
+ * pixel's composited fragments, transmittance recovered from T_final (no
+ * per-fragment state), per-wavefront reduction before atomics into
+ * proj->g2d, then one thread per triangle chains the 2D gradients to the
+ * vertices, opacity, sigma and SH coefficients.
+ *   dL_drgb [3][H][W] required; dL_dalpha, dL_ddepth [H][W] may be NULL.
+ *   T_final, last: the forward outputs of the same view.
+ * Gradients are overwritten (not accumulated); culled triangles get zeros.
+ *   gv [N][3][3], go [N], gsigma [N], gsh [N][(deg+1)^2][3]
+ */
+int ts_render_backward(const float* v, const float* o, const float* sigma, const float* sh,
+                       int64_t N, const ts_proj* proj, const ts_bins* bins,
+                       const ts_camera* cam, const ts_config* cfg, const float* dL_drgb,
+                       const float* dL_dalpha, const float* dL_ddepth, const float* T_final,
+                       const uint32_t* last, float* gv, float* go, float* gsigma, float* gsh,
+                       hipStream_t stream);
+
+/* Static description of an error code. */
+const char* ts_error_string(int code);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* ts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TS_H */

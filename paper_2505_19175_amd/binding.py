@@ -1,0 +1,188 @@
+"""Python binding of libts.so: the C ABI of include/ts.h, argument
+marshalling only.
+
+Every function below has the name of the C entry point it calls and takes
+device pointers as ints or torch tensors (their data_ptr is passed).  All
+computation happens in the library's HIP kernels; there is no fallback:
+loading fails loudly when libts.so is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libts.so")
+
+TS_OK = 0
+TS_EINVAL = 1
+TS_ECAPACITY = 2
+TS_EWORKSPACE = 3
+TS_EHIP = 4
+TS_TILE = 16
+TS_G2D_STRIDE = 16
+
+EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
+           "ts_bin_sort", "ts_render_forward", "ts_render_backward", "ts_error_string",
+           "ts_last_error")
+
+
+class TSError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed with code {code}: {msg}")
+        self.code = code
+
+
+class ts_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class ts_config(ctypes.Structure):
+    _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("T_min", ctypes.c_float), ("z_near", ctypes.c_float), ("r_min", ctypes.c_float),
+                ("sh_degree", ctypes.c_int32), ("bg", ctypes.c_float * 3)]
+
+
+class ts_proj(ctypes.Structure):
+    _fields_ = [("rec", ctypes.c_void_p), ("rect", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("ntiles", ctypes.c_void_p), ("g2d", ctypes.c_void_p)]
+
+
+class ts_bins(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("ranges", ctypes.c_void_p), ("d_count", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libts.so (built by paper_2505_19175_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2505_19175_amd.build` (there is no fallback path)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, U64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    PC, PG = ctypes.POINTER(ts_camera), ctypes.POINTER(ts_config)
+    PP, PB = ctypes.POINTER(ts_proj), ctypes.POINTER(ts_bins)
+    L.ts_proj_record_bytes.restype = ctypes.c_size_t
+    L.ts_proj_record_bytes.argtypes = []
+    L.ts_num_tiles.restype = ctypes.c_int32
+    L.ts_num_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.ts_bin_sort_workspace_bytes.restype = ctypes.c_size_t
+    L.ts_bin_sort_workspace_bytes.argtypes = [I64, U64, ctypes.c_int32]
+    L.ts_project.restype = ctypes.c_int
+    L.ts_project.argtypes = [P, P, P, P, I64, PC, PG, PP, P]
+    L.ts_bin_sort.restype = ctypes.c_int
+    L.ts_bin_sort.argtypes = [PP, I64, PC, P, ctypes.c_size_t, PB, P, P]
+    L.ts_render_forward.restype = ctypes.c_int
+    L.ts_render_forward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
+    L.ts_render_backward.restype = ctypes.c_int
+    L.ts_render_backward.argtypes = [P, P, P, P, I64, PP, PB, PC, PG, P, P, P, P, P, P, P, P, P, P]
+    L.ts_error_string.restype = ctypes.c_char_p
+    L.ts_error_string.argtypes = [ctypes.c_int]
+    L.ts_last_error.restype = ctypes.c_char_p
+    L.ts_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _check(rc: int, where: str):
+    if rc != TS_OK:
+        L = load()
+        raise TSError(rc, where, (L.ts_last_error() or b"").decode() or
+                      L.ts_error_string(rc).decode())
+
+
+# ---------------------------------------------------------------------------
+# The C ABI, name for name
+# ---------------------------------------------------------------------------
+
+def ts_proj_record_bytes() -> int:
+    return int(load().ts_proj_record_bytes())
+
+
+def ts_num_tiles(width: int, height: int) -> int:
+    return int(load().ts_num_tiles(width, height))
+
+
+def ts_bin_sort_workspace_bytes(N: int, capacity: int, num_tiles: int) -> int:
+    return int(load().ts_bin_sort_workspace_bytes(N, capacity, num_tiles))
+
+
+def ts_project(v, o, sigma, sh, N: int, cam: ts_camera, cfg: ts_config, out: ts_proj,
+               stream: int = 0):
+    _check(load().ts_project(_ptr(v), _ptr(o), _ptr(sigma), _ptr(sh), N, ctypes.byref(cam),
+                             ctypes.byref(cfg), ctypes.byref(out), stream), "ts_project")
+
+
+def ts_bin_sort(proj: ts_proj, N: int, cam: ts_camera, ws, ws_bytes: int, out: ts_bins,
+                h_count=None, stream: int = 0):
+    """h_count: None (no host sync) or a ctypes uint32 array of 2."""
+    hc = None if h_count is None else ctypes.cast(h_count, ctypes.c_void_p)
+    _check(load().ts_bin_sort(ctypes.byref(proj), N, ctypes.byref(cam), _ptr(ws), ws_bytes,
+                              ctypes.byref(out), hc, stream), "ts_bin_sort")
+
+
+def ts_render_forward(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config, rgb, alpha,
+                      depth, T_final, last, stream: int = 0):
+    _check(load().ts_render_forward(ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(cam),
+                                    ctypes.byref(cfg), _ptr(rgb), _ptr(alpha), _ptr(depth),
+                                    _ptr(T_final), _ptr(last), stream), "ts_render_forward")
+
+
+def ts_render_backward(v, o, sigma, sh, N: int, proj: ts_proj, bins: ts_bins, cam: ts_camera,
+                       cfg: ts_config, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, gv, go,
+                       gsigma, gsh, stream: int = 0):
+    _check(load().ts_render_backward(_ptr(v), _ptr(o), _ptr(sigma), _ptr(sh), N,
+                                     ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(cam),
+                                     ctypes.byref(cfg), _ptr(dL_drgb), _ptr(dL_dalpha),
+                                     _ptr(dL_ddepth), _ptr(T_final), _ptr(last), _ptr(gv),
+                                     _ptr(go), _ptr(gsigma), _ptr(gsh), stream),
+           "ts_render_backward")
+
+
+def ts_error_string(code: int) -> str:
+    return load().ts_error_string(code).decode()
+
+
+def ts_last_error() -> str:
+    return (load().ts_last_error() or b"").decode()
+
+
+# ---------------------------------------------------------------------------
+# Struct builders from the plain containers of paper_2505_19175_amd.synth
+# ---------------------------------------------------------------------------
+
+def make_camera(cam) -> ts_camera:
+    c = ts_camera()
+    R = [float(x) for x in __import__("numpy").asarray(cam.R, "float32").reshape(9)]
+    t = [float(x) for x in __import__("numpy").asarray(cam.t, "float32").reshape(3)]
+    c.R[:] = R
+    c.t[:] = t
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def make_config(cfg) -> ts_config:
+    g = ts_config()
+    g.alpha_min, g.alpha_max, g.T_min = float(cfg.alpha_min), float(cfg.alpha_max), float(cfg.T_min)
+    g.z_near, g.r_min = float(cfg.z_near), float(cfg.r_min)
+    g.sh_degree = int(cfg.sh_degree)
+    g.bg[:] = [float(b) for b in cfg.bg]
+    return g

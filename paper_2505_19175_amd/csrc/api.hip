@@ -1,0 +1,202 @@
+// api.hip -- extern "C" entry points of libts.so: argument checks, workspace
+// carve-up and kernel launches.  No allocation happens here.
+#include <stdio.h>
+#include <string.h>
+
+#include "ts_device.h"
+#include "ts_kernels.h"
+
+namespace {
+
+thread_local char g_msg[256] = "";
+
+int fail(int code, const char* what)
+{
+    snprintf(g_msg, sizeof g_msg, "%s", what);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    snprintf(g_msg, sizeof g_msg, "%s: %s", where, hipGetErrorString(e));
+    return TS_EHIP;
+}
+
+bool cam_ok(const ts_camera* c)
+{
+    return c && c->width > 0 && c->height > 0 && c->width <= TS_MAX_IMAGE_DIM &&
+           c->height <= TS_MAX_IMAGE_DIM;
+}
+
+bool cfg_ok(const ts_config* g)
+{
+    return g && g->sh_degree >= 0 && g->sh_degree <= TS_MAX_SH_DEGREE && g->alpha_max > 0.f &&
+           g->alpha_max <= 1.f && g->alpha_min >= 0.f && g->alpha_min < g->alpha_max &&
+           g->T_min >= 0.f;
+}
+
+ts::Cam to_cam(const ts_camera* c)
+{
+    ts::Cam k;
+    memcpy(k.R, c->R, sizeof k.R);
+    memcpy(k.t, c->t, sizeof k.t);
+    k.fx = c->fx; k.fy = c->fy; k.cx = c->cx; k.cy = c->cy;
+    k.W = c->width; k.H = c->height;
+    return k;
+}
+
+ts::Cfg to_cfg(const ts_config* g)
+{
+    ts::Cfg k;
+    k.alpha_min = g->alpha_min; k.alpha_max = g->alpha_max; k.T_min = g->T_min;
+    k.z_near = g->z_near; k.r_min = g->r_min; k.deg = g->sh_degree;
+    k.bg[0] = g->bg[0]; k.bg[1] = g->bg[1]; k.bg[2] = g->bg[2];
+    return k;
+}
+
+int tiles_x_of(const ts_camera* c) { return (c->width + TS_TILE - 1) / TS_TILE; }
+
+bool proj_ok(const ts_proj* p)
+{
+    return p && p->rec && p->rect && p->depth && p->ntiles && p->g2d &&
+           (reinterpret_cast<uintptr_t>(p->rec) & 15u) == 0 &&
+           (reinterpret_cast<uintptr_t>(p->rect) & 7u) == 0 &&
+           (reinterpret_cast<uintptr_t>(p->g2d) & 15u) == 0;
+}
+
+bool bins_ok(const ts_bins* b)
+{
+    return b && b->vals && b->ranges && b->d_count && b->capacity <= 0xffffffffull;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ts_proj_record_bytes(void) { return sizeof(ts::TriRecord); }
+
+int32_t ts_num_tiles(int32_t width, int32_t height)
+{
+    if (width <= 0 || height <= 0) return 0;
+    return ((width + TS_TILE - 1) / TS_TILE) * ((height + TS_TILE - 1) / TS_TILE);
+}
+
+size_t ts_bin_sort_workspace_bytes(int64_t N, uint64_t capacity, int32_t num_tiles)
+{
+    (void)num_tiles;
+    if (N < 0) return 0;
+    return ts::carve_bin_workspace(nullptr, N, capacity).bytes;
+}
+
+int ts_project(const float* v, const float* o, const float* sigma, const float* sh, int64_t N,
+               const ts_camera* cam, const ts_config* cfg, const ts_proj* out,
+               hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_project: N out of range");
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_project: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_project: bad config");
+    if (N == 0) return TS_OK;
+    if (!v || !o || !sigma || !sh || !proj_ok(out))
+        return fail(TS_EINVAL, "ts_project: null or misaligned pointer");
+    ts::launch_project(v, o, sigma, sh, N, to_cam(cam), to_cfg(cfg), out->rec, out->rect,
+                       out->depth, out->ntiles, out->g2d, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project");
+}
+
+int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, size_t ws_bytes,
+                const ts_bins* out, uint32_t* h_count, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_bin_sort: N out of range");
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_bin_sort: bad camera");
+    if (!bins_ok(out)) return fail(TS_EINVAL, "ts_bin_sort: bad bins");
+    if (N > 0 && !proj_ok(proj)) return fail(TS_EINVAL, "ts_bin_sort: bad projection");
+    const int num_tiles = ts_num_tiles(cam->width, cam->height);
+    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, N, out->capacity);
+    if (!ws || ws_bytes < need.bytes) return fail(TS_EWORKSPACE, "ts_bin_sort: workspace too small");
+    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, N, out->capacity);
+    bool overflow = false;
+    hipError_t e;
+    if (N == 0) {
+        // empty scene: zero counts and ranges
+        ts::launch_fill_u32(out->d_count, 4, 0u, stream);
+        ts::launch_fill_u32(out->ranges, 2 * (int64_t)num_tiles, 0u, stream);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "ts_bin_sort");
+        if (h_count) {
+            h_count[0] = 0;
+            h_count[1] = 0;
+        }
+        return TS_OK;
+    }
+    e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, N, tiles_x_of(cam), num_tiles, w,
+                         *out, h_count, &overflow, stream);
+    if (e != hipSuccess) return hip_fail(e, "ts_bin_sort");
+    if (overflow) return fail(TS_ECAPACITY, "ts_bin_sort: instances exceed capacity");
+    return TS_OK;
+}
+
+int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                      const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                      float* T_final, uint32_t* last, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_render_forward: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_forward: bad config");
+    if (!bins_ok(bins) || !proj || !proj->rec)
+        return fail(TS_EINVAL, "ts_render_forward: bad projection or bins");
+    if (!rgb || !alpha || !depth || !T_final || !last)
+        return fail(TS_EINVAL, "ts_render_forward: null output");
+    ts::launch_raster_forward(proj->rec, bins->vals, bins->ranges, to_cam(cam), to_cfg(cfg),
+                              tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), rgb,
+                              alpha, depth, T_final, last, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward");
+}
+
+int ts_render_backward(const float* v, const float* o, const float* sigma, const float* sh,
+                       int64_t N, const ts_proj* proj, const ts_bins* bins,
+                       const ts_camera* cam, const ts_config* cfg, const float* dL_drgb,
+                       const float* dL_dalpha, const float* dL_ddepth, const float* T_final,
+                       const uint32_t* last, float* gv, float* go, float* gsigma, float* gsh,
+                       hipStream_t stream)
+{
+    g_msg[0] = 0;
+    (void)o;
+    (void)sigma;
+    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_render_backward: N out of range");
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_render_backward: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_backward: bad config");
+    if (!bins_ok(bins)) return fail(TS_EINVAL, "ts_render_backward: bad bins");
+    if (N > 0 && (!proj_ok(proj) || !v || !sh || !gv || !go || !gsigma || !gsh))
+        return fail(TS_EINVAL, "ts_render_backward: null pointer");
+    if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_render_backward: null upstream");
+    if (N == 0) return TS_OK;
+    const ts::Cam k = to_cam(cam);
+    const ts::Cfg g = to_cfg(cfg);
+    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, k, g, tiles_x_of(cam),
+                               ts_num_tiles(cam->width, cam->height), dL_drgb, dL_dalpha,
+                               dL_ddepth, T_final, last, proj->g2d, stream);
+    ts::launch_backproject(v, sh, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go, gsigma,
+                           gsh, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_backward");
+}
+
+const char* ts_error_string(int code)
+{
+    switch (code) {
+    case TS_OK: return "ok";
+    case TS_EINVAL: return "invalid argument";
+    case TS_ECAPACITY: return "instance count exceeds capacity";
+    case TS_EWORKSPACE: return "workspace too small";
+    case TS_EHIP: return "HIP error";
+    default: return "unknown error";
+    }
+}
+
+const char* ts_last_error(void) { return g_msg; }
+
+}  // extern "C"

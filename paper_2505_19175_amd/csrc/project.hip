@@ -1,0 +1,360 @@
+// project.hip -- per-triangle kernels: projection + window set-up + SH colour
+// (forward) and the chain from 2D gradients to the triangle parameters
+// (backward).  One thread per triangle; geometry in FP64.
+#include "ts_device.h"
+#include "ts_kernels.h"
+
+namespace ts {
+
+// Camera-space and projected vertices with the edge quantities every
+// consumer needs.  Edge k runs from q_k to q_{k+1}.
+struct Geo {
+    double xc[3][3];
+    double q[3][2];
+    double e[3][2];
+    double len[3];
+    double S;     // signed doubled area
+    double P;     // perimeter
+    bool front;   // every vertex beyond the near plane
+};
+
+__device__ __forceinline__ void load_vertices(const float* __restrict__ v, int64_t i, float vv[9])
+{
+    const float* p = v + 9 * i;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) vv[a] = p[a];
+}
+
+__device__ __forceinline__ void project_geo(const float vv[9], const Cam& cam, float z_near, Geo& g)
+{
+    g.front = true;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double acc = (double)cam.t[a];
+            acc = fma((double)cam.R[3 * a + 0], (double)vv[3 * j + 0], acc);
+            acc = fma((double)cam.R[3 * a + 1], (double)vv[3 * j + 1], acc);
+            acc = fma((double)cam.R[3 * a + 2], (double)vv[3 * j + 2], acc);
+            g.xc[j][a] = acc;
+        }
+        g.front = g.front && (g.xc[j][2] > (double)z_near);
+        const double iz = 1.0 / g.xc[j][2];
+        g.q[j][0] = fma((double)cam.fx * g.xc[j][0], iz, (double)cam.cx);
+        g.q[j][1] = fma((double)cam.fy * g.xc[j][1], iz, (double)cam.cy);
+    }
+    g.P = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        g.e[k][0] = g.q[k1][0] - g.q[k][0];
+        g.e[k][1] = g.q[k1][1] - g.q[k][1];
+        g.len[k] = sqrt(g.e[k][0] * g.e[k][0] + g.e[k][1] * g.e[k][1]);
+        g.P += g.len[k];
+    }
+    // 2A = cross(q1 - q0, q2 - q0)
+    g.S = g.e[0][0] * (g.q[2][1] - g.q[0][1]) - g.e[0][1] * (g.q[2][0] - g.q[0][0]);
+}
+
+// Depth key: mean camera-space z of the three vertices, every operation
+// rounded in the written order (no contraction), so the float32 key is a
+// fixed function of the inputs: z_j = ((R20 v0 + R21 v1) + R22 v2) + t2,
+// z_c = ((z_0 + z_1) + z_2) / 3.
+__device__ __forceinline__ double depth_centre(const float vv[9], const Cam& cam)
+{
+    double zs = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double z = __dmul_rn((double)cam.R[6], (double)vv[3 * j + 0]);
+        z = __dadd_rn(z, __dmul_rn((double)cam.R[7], (double)vv[3 * j + 1]));
+        z = __dadd_rn(z, __dmul_rn((double)cam.R[8], (double)vv[3 * j + 2]));
+        z = __dadd_rn(z, (double)cam.t[2]);
+        zs = j == 0 ? z : __dadd_rn(zs, z);
+    }
+    return zs / 3.0;
+}
+
+// Unit direction from the camera centre -R^T t to the centroid, and its norm.
+__device__ __forceinline__ void view_dir(const float vv[9], const Cam& cam, double d[3], double& nrm)
+{
+    double dv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double cen = ((double)vv[a] + (double)vv[3 + a] + (double)vv[6 + a]) * (1.0 / 3.0);
+        const double cc = -((double)cam.R[a] * cam.t[0] + (double)cam.R[3 + a] * cam.t[1] +
+                            (double)cam.R[6 + a] * cam.t[2]);
+        dv[a] = cen - cc;
+    }
+    nrm = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = dv[a] / nrm;
+}
+
+// ---------------------------------------------------------------------------
+// Forward: project, cull, tight box, window coefficients, SH colour.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_project(
+    const float* __restrict__ v, const float* __restrict__ o, const float* __restrict__ sigma,
+    const float* __restrict__ sh, int64_t N, Cam cam, Cfg cfg, TriRecord* __restrict__ rec,
+    short4* __restrict__ rect, float* __restrict__ depth, uint32_t* __restrict__ ntiles,
+    float4* __restrict__ g2d)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+
+    float vv[9];
+    load_vertices(v, i, vv);
+    const float oi = o[i];
+    const float si = sigma[i];
+    Geo g;
+    project_geo(vv, cam, cfg.z_near, g);
+    const double zc = depth_centre(vv, cam);
+    depth[i] = (float)zc;
+
+    const double r = g.P > 0.0 ? fabs(g.S) / g.P : 0.0;
+    bool vis = g.front && (r >= (double)cfg.r_min) && (oi >= cfg.alpha_min) && (si > 0.f);
+
+    // Tight region {o I >= alpha_min} = {u >= u_min}: the triangle scaled
+    // about its incentre by 1 - u_min, u_min = (alpha_min/o)^(1/sigma).
+    int px0 = 0, px1 = -1, py0 = 0, py1 = -1;
+    if (vis) {
+        const double sx = (g.len[1] * g.q[0][0] + g.len[2] * g.q[1][0] + g.len[0] * g.q[2][0]) / g.P;
+        const double sy = (g.len[1] * g.q[0][1] + g.len[2] * g.q[1][1] + g.len[0] * g.q[2][1]) / g.P;
+        const double umin = pow((double)cfg.alpha_min / (double)oi, 1.0 / (double)si);
+        const double f = 1.0 - umin;
+        double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double x = fma(f, g.q[j][0] - sx, sx);
+            const double y = fma(f, g.q[j][1] - sy, sy);
+            xmin = fmin(xmin, x); xmax = fmax(xmax, x);
+            ymin = fmin(ymin, y); ymax = fmax(ymax, y);
+        }
+        const double fx0 = fmax(0.0, ceil(xmin - 0.5));
+        const double fx1 = fmin((double)(cam.W - 1), floor(xmax - 0.5));
+        const double fy0 = fmax(0.0, ceil(ymin - 0.5));
+        const double fy1 = fmin((double)(cam.H - 1), floor(ymax - 0.5));
+        if (fx0 <= fx1 && fy0 <= fy1) {   // false for NaN as well
+            px0 = (int)fx0; px1 = (int)fx1; py0 = (int)fy0; py1 = (int)fy1;
+        } else {
+            vis = false;
+        }
+    }
+    if (!vis) {
+        ntiles[i] = 0u;
+        rect[i] = make_short4(0, -1, 0, -1);
+        return;
+    }
+    rect[i] = make_short4((short)px0, (short)px1, (short)py0, (short)py1);
+    ntiles[i] = (uint32_t)((px1 / kTile - px0 / kTile + 1) * (py1 / kTile - py0 / kTile + 1));
+
+    TriRecord R;
+    // u_k(p) = w_k cross(e_k, p - q_k), w_k = P / (2A l_k), relative to the anchor
+    const double ax = (double)px0, ay = (double)py0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double w = g.P / (g.S * g.len[k]);
+        const double qx = g.q[k][0] - ax, qy = g.q[k][1] - ay;
+        R.A[k] = -w * g.e[k][1];
+        R.B[k] = w * g.e[k][0];
+        R.C[k] = w * (g.e[k][0] * (0.5 - qy) - g.e[k][1] * (0.5 - qx));
+    }
+    R.ax = px0;
+    R.ay = py0;
+    R.o = oi;
+    R.sigma = si;
+    R.z = (float)zc;
+    R.px0 = (int16_t)px0; R.px1 = (int16_t)px1; R.py0 = (int16_t)py0; R.py1 = (int16_t)py1;
+    R.tri = (uint32_t)i;
+    R.pad[0] = R.pad[1] = R.pad[2] = 0.f;
+
+    // colour: real SH along the view direction, + 1/2, clamped at zero
+    double d[3], nrm;
+    view_dir(vv, cam, d, nrm);
+    float Y[16];
+    sh_basis(cfg.deg, (float)d[0], (float)d[1], (float)d[2], Y);
+    const int K = (cfg.deg + 1) * (cfg.deg + 1);
+    const float* c = sh + (int64_t)K * 3 * i;
+    float acc[3] = {0.5f, 0.5f, 0.5f};
+    for (int k = 0; k < K; ++k) {
+        acc[0] = fmaf(c[3 * k + 0], Y[k], acc[0]);
+        acc[1] = fmaf(c[3 * k + 1], Y[k], acc[1]);
+        acc[2] = fmaf(c[3 * k + 2], Y[k], acc[2]);
+    }
+    R.rgb[0] = fmaxf(acc[0], 0.f);
+    R.rgb[1] = fmaxf(acc[1], 0.f);
+    R.rgb[2] = fmaxf(acc[2], 0.f);
+
+    const float4* src = reinterpret_cast<const float4*>(&R);
+    float4* dst = reinterpret_cast<float4*>(rec + i);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[j] = src[j];
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g2d[4 * i + j] = z4;
+}
+
+// ---------------------------------------------------------------------------
+// Backward: 2D accumulators -> window coefficients -> projected vertices ->
+// camera space -> world vertices; colour -> SH coefficients and view
+// direction.  Consumes g2d (re-zeroes it).
+// g2d slots: 0-2 dL/dA_k, 3-5 dL/dB_k, 6-8 dL/dC_k, 9 dL/do, 10 dL/dsigma,
+//            11-13 dL/drgb, 14 dL/dz.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_backproject(
+    const float* __restrict__ v, const float* __restrict__ sh, int64_t N, Cam cam, Cfg cfg,
+    const short4* __restrict__ rect, const uint32_t* __restrict__ ntiles,
+    float4* __restrict__ g2d, float* __restrict__ gv, float* __restrict__ go,
+    float* __restrict__ gsig, float* __restrict__ gsh)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int K = (cfg.deg + 1) * (cfg.deg + 1);
+    float* gshi = gsh + (int64_t)K * 3 * i;
+    float* gvi = gv + 9 * i;
+    if (ntiles[i] == 0u) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gvi[a] = 0.f;
+        for (int a = 0; a < 3 * K; ++a) gshi[a] = 0.f;
+        go[i] = 0.f;
+        gsig[i] = 0.f;
+        return;
+    }
+    float G[16];
+    {
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float4 t = g2d[4 * i + j];
+            G[4 * j + 0] = t.x; G[4 * j + 1] = t.y; G[4 * j + 2] = t.z; G[4 * j + 3] = t.w;
+            g2d[4 * i + j] = z4;
+        }
+    }
+    go[i] = G[9];
+    gsig[i] = G[10];
+
+    float vv[9];
+    load_vertices(v, i, vv);
+    Geo g;
+    project_geo(vv, cam, cfg.z_near, g);
+    const short4 rc = rect[i];
+    const double ax = (double)rc.x, ay = (double)rc.z;
+
+    // coefficients -> (w_k, e_k, q_k)
+    double gq[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    double ge[3][2];
+    double gP = 0.0, gS = 0.0, gl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double w = g.P / (g.S * g.len[k]);
+        const double qx = g.q[k][0] - ax, qy = g.q[k][1] - ay;
+        const double ex = g.e[k][0], ey = g.e[k][1];
+        const double gA = G[k], gB = G[3 + k], gC = G[6 + k];
+        const double ck = ex * (0.5 - qy) - ey * (0.5 - qx);
+        const double gw = -gA * ey + gB * ex + gC * ck;
+        ge[k][0] = gB * w + gC * w * (0.5 - qy);
+        ge[k][1] = -gA * w - gC * w * (0.5 - qx);
+        gq[k][0] += gC * w * ey;
+        gq[k][1] += -gC * w * ex;
+        // w = P / (S l_k)
+        gP += gw / (g.S * g.len[k]);
+        gS += -gw * w / g.S;
+        gl[k] = -gw * w / g.len[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double gl_k = gl[k] + gP;               // P = sum l_k
+        ge[k][0] += gl_k * g.e[k][0] / g.len[k];      // l_k = |e_k|
+        ge[k][1] += gl_k * g.e[k][1] / g.len[k];
+    }
+    // S = x0 (y1 - y2) + x1 (y2 - y0) + x2 (y0 - y1)
+    gq[0][0] += gS * (g.q[1][1] - g.q[2][1]);
+    gq[0][1] += gS * (g.q[2][0] - g.q[1][0]);
+    gq[1][0] += gS * (g.q[2][1] - g.q[0][1]);
+    gq[1][1] += gS * (g.q[0][0] - g.q[2][0]);
+    gq[2][0] += gS * (g.q[0][1] - g.q[1][1]);
+    gq[2][1] += gS * (g.q[1][0] - g.q[0][0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {                     // e_k = q_{k+1} - q_k
+        const int k1 = k == 2 ? 0 : k + 1;
+        gq[k1][0] += ge[k][0]; gq[k1][1] += ge[k][1];
+        gq[k][0] -= ge[k][0];  gq[k][1] -= ge[k][1];
+    }
+
+    // projection q = (fx x/z + cx, fy y/z + cy); depth key = mean z
+    const double gz3 = (double)G[14] * (1.0 / 3.0);
+    double gw_[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double x = g.xc[j][0], y = g.xc[j][1], z = g.xc[j][2];
+        const double iz = 1.0 / z;
+        const double gx0 = cam.fx * iz * gq[j][0];
+        const double gx1 = cam.fy * iz * gq[j][1];
+        const double gx2 = -(cam.fx * x * gq[j][0] + cam.fy * y * gq[j][1]) * iz * iz + gz3;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)                   // R^T gx
+            gw_[j][b] = (double)cam.R[b] * gx0 + (double)cam.R[3 + b] * gx1 + (double)cam.R[6 + b] * gx2;
+    }
+
+    // colour: rgb = max(0, sum_k sh_k Y_k(d) + 1/2)
+    double d[3], nrm;
+    view_dir(vv, cam, d, nrm);
+    const float dx = (float)d[0], dy = (float)d[1], dz = (float)d[2];
+    float Y[16], dY[16][3];
+    sh_basis(cfg.deg, dx, dy, dz, Y);
+    sh_basis_grad(cfg.deg, dx, dy, dz, dY);
+    const float* c = sh + (int64_t)K * 3 * i;
+    float raw[3] = {0.5f, 0.5f, 0.5f};
+    for (int k = 0; k < K; ++k) {
+        raw[0] = fmaf(c[3 * k + 0], Y[k], raw[0]);
+        raw[1] = fmaf(c[3 * k + 1], Y[k], raw[1]);
+        raw[2] = fmaf(c[3 * k + 2], Y[k], raw[2]);
+    }
+    const float gr0 = raw[0] > 0.f ? G[11] : 0.f;
+    const float gr1 = raw[1] > 0.f ? G[12] : 0.f;
+    const float gr2 = raw[2] > 0.f ? G[13] : 0.f;
+    float gd[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < K; ++k) {
+        gshi[3 * k + 0] = gr0 * Y[k];
+        gshi[3 * k + 1] = gr1 * Y[k];
+        gshi[3 * k + 2] = gr2 * Y[k];
+        const float s = gr0 * c[3 * k + 0] + gr1 * c[3 * k + 1] + gr2 * c[3 * k + 2];
+        gd[0] = fmaf(s, dY[k][0], gd[0]);
+        gd[1] = fmaf(s, dY[k][1], gd[1]);
+        gd[2] = fmaf(s, dY[k][2], gd[2]);
+    }
+    // d = dv/|dv|, dv = centroid - camera centre, centroid = mean of vertices
+    const double dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double gdv = ((double)gd[b] - d[b] * dd) / nrm * (1.0 / 3.0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gw_[j][b] += gdv;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gvi[3 * j + b] = (float)gw_[j][b];
+}
+
+void launch_project(const float* v, const float* o, const float* sigma, const float* sh,
+                    int64_t N, const Cam& cam, const Cfg& cfg, void* rec, int16_t* rect,
+                    float* depth, uint32_t* ntiles, float* g2d, hipStream_t stream)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, stream, v, o, sigma, sh, N,
+                       cam, cfg, reinterpret_cast<TriRecord*>(rec), reinterpret_cast<short4*>(rect),
+                       depth, ntiles, reinterpret_cast<float4*>(g2d));
+}
+
+void launch_backproject(const float* v, const float* sh, int64_t N, const Cam& cam,
+                        const Cfg& cfg, const int16_t* rect, const uint32_t* ntiles, float* g2d,
+                        float* gv, float* go, float* gsig, float* gsh, hipStream_t stream)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL(k_backproject, dim3((unsigned)blocks), dim3(256), 0, stream, v, sh, N, cam,
+                       cfg, reinterpret_cast<const short4*>(rect), ntiles,
+                       reinterpret_cast<float4*>(g2d), gv, go, gsig, gsh);
+}
+
+}  // namespace ts

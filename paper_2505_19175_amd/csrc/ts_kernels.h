@@ -1,0 +1,60 @@
+// ts_kernels.h -- host-side launchers of the gfx950 kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ts.h"
+
+namespace ts {
+
+struct Cam;
+struct Cfg;
+
+void launch_project(const float* v, const float* o, const float* sigma, const float* sh,
+                    int64_t N, const Cam& cam, const Cfg& cfg, void* rec, int16_t* rect,
+                    float* depth, uint32_t* ntiles, float* g2d, hipStream_t stream);
+
+void launch_backproject(const float* v, const float* sh, int64_t N, const Cam& cam,
+                        const Cfg& cfg, const int16_t* rect, const uint32_t* ntiles, float* g2d,
+                        float* gv, float* go, float* gsig, float* gsh, hipStream_t stream);
+
+// p[0..n) = x (a kernel, so it can sit inside a captured graph).
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream);
+
+// Workspace carve-up of the binning stage.
+struct BinWorkspace {
+    uint32_t* blk;      // [nbN + 1] block sums / offsets
+    uint32_t* dk[2];    // [N] depth keys (ping-pong)
+    uint32_t* dv[2];    // [N] triangle ids (ping-pong)
+    uint32_t* off;      // [N] first instance of each depth-sorted triangle
+    uint32_t* hist;     // [256][hist_stride] radix block histograms
+    uint32_t* dtot;     // [256] radix digit totals
+    uint32_t* tk[2];    // [capacity] tile ids (ping-pong)
+    uint32_t* tv[2];    // [capacity] triangle ids (ping-pong)
+    uint32_t* tfin;     // [capacity] sorted tile ids
+    uint32_t* ctl;      // [8] device counters: [0] sort count min(M, capacity)
+    int64_t hist_stride;
+    size_t bytes;
+};
+
+BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity);
+
+// Device-side binning: returns hipSuccess or the first launch error.
+hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_t* rect,
+                        int64_t N, int tiles_x, int num_tiles, const BinWorkspace& ws,
+                        const ts_bins& out, uint32_t* h_count, bool* overflow,
+                        hipStream_t stream);
+
+void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
+                           const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
+                           float* rgb, float* alpha, float* depth, float* T_final,
+                           uint32_t* last, hipStream_t stream);
+
+void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
+                            const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
+                            const float* dL_drgb, const float* dL_dalpha,
+                            const float* dL_ddepth, const float* T_final,
+                            const uint32_t* last, float* g2d, hipStream_t stream);
+
+}  // namespace ts

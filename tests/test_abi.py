@@ -1,0 +1,79 @@
+"""The C ABI without a GPU: libts.so loads, exports every function that
+include/ts.h declares, the Python binding covers them all, and the ctypes
+struct layouts equal the header's (measured by compiling a C probe)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2505_19175_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ts.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ts_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_hot_path_calls():
+    fns = declared_functions()
+    for name in ("ts_project", "ts_bin_sort", "ts_render_forward", "ts_render_backward"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(B.EXPORTS) == declared_functions()
+
+
+def test_host_only_queries():
+    assert B.ts_proj_record_bytes() == 128
+    assert B.ts_num_tiles(1280, 720) == 80 * 45
+    assert B.ts_num_tiles(1600, 1040) == 100 * 65
+    assert B.ts_num_tiles(17, 1) == 2
+    a = B.ts_bin_sort_workspace_bytes(1000, 5000, 64)
+    b = B.ts_bin_sort_workspace_bytes(1000, 50000, 64)
+    assert 0 < a < b
+    assert B.ts_error_string(B.TS_ECAPACITY) == "instance count exceeds capacity"
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ts.h"
+#define P(T, F) printf(#T "." #F " %zu\n", offsetof(T, F))
+int main(void) {
+  printf("ts_camera %zu\n", sizeof(ts_camera)); P(ts_camera, t); P(ts_camera, fx); P(ts_camera, width);
+  printf("ts_config %zu\n", sizeof(ts_config)); P(ts_config, sh_degree); P(ts_config, bg);
+  printf("ts_proj %zu\n", sizeof(ts_proj)); P(ts_proj, g2d);
+  printf("ts_bins %zu\n", sizeof(ts_bins)); P(ts_bins, d_count); P(ts_bins, capacity);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(PROBE)
+        subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                               "-I", "/opt/rocm/include", src, "-o", exe])
+        lines = subprocess.check_output([exe], text=True).split("\n")
+    got = dict(l.split() for l in lines if l)
+    ct = {"ts_camera": B.ts_camera, "ts_config": B.ts_config, "ts_proj": B.ts_proj,
+          "ts_bins": B.ts_bins}
+    for k, v in got.items():
+        if "." in k:
+            s, f = k.split(".")
+            assert getattr(ct[s], f).offset == int(v), k
+        else:
+            assert ctypes.sizeof(ct[k]) == int(v), k

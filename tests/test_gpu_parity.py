@@ -1,0 +1,254 @@
+"""GPU parity: the C-ABI HIP path against the FP64 oracle, per stage.
+
+  projection   depth keys bit-exact, tight boxes / tile counts exact
+  binning      sorted keys, values and tile ranges bit-exact
+  forward      |delta| <= 1e-5 per channel on every unflagged pixel
+  backward     per element 1e-3 relative (+1e-6 of the group's max) and
+               1e-3 relative L2 per group, upstream zeroed on flagged pixels
+
+Small workloads are compared on the full frame; the 300k and 3M triangle
+workloads on a seeded sample of 4,096 pixels (the oracle's cost is
+O(pixels x triangles))."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2505_19175_amd import synth
+from paper_2505_19175_amd.synth import Config
+
+import gpu_util as G
+from helpers import random_soup
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases_small():
+    wl = synth.workload_small()
+    return wl.scene, wl.cameras[0], wl.config, wl.upstream_seed
+
+
+@pytest.fixture(scope="module")
+def small():
+    return _cases_small()
+
+
+def _check_projection(st, scene, cam, cfg):
+    ref = O.setup(scene, cam, cfg)
+    depth = st.depth_key.cpu().numpy()[: scene.n]
+    assert np.array_equal(depth.view(np.uint32), ref["key"].view(np.uint32))
+    nt = st.ntiles.cpu().numpy()[: scene.n].astype(np.int64)
+    np.testing.assert_array_equal(nt, ref["ntiles"])
+    vis = ref["ntiles"] > 0
+    rect = st.rect.cpu().numpy()[: scene.n].astype(np.int64)
+    np.testing.assert_array_equal(rect[vis], ref["rect"][vis])
+    return int(vis.sum())
+
+
+def _check_bins(st, scene, cam, cfg):
+    ref = O.bin_instances(scene, cam, cfg)
+    M = st.M
+    assert M == ref["count"]
+    vals = st.vals.cpu().numpy()[:M].view(np.uint32)
+    keys = st.keys.cpu().numpy()[:M].view(np.uint64)
+    np.testing.assert_array_equal(vals, ref["vals"])
+    np.testing.assert_array_equal(keys, ref["keys"])
+    ranges = st.ranges.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(ranges, ref["ranges"])
+    dc = st.d_count.cpu().numpy()
+    assert dc[0] == M and dc[1] == int((ref["setup"]["ntiles"] > 0).sum()) and dc[2] == 0
+    return M
+
+
+# ---------------------------------------------------------------------------
+# 1k triangles, 128x128, full frame
+# ---------------------------------------------------------------------------
+
+def test_small_projection_and_bins(small):
+    scene, cam, cfg, _ = small
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    nvis = _check_projection(st, scene, cam, cfg)
+    M = _check_bins(st, scene, cam, cfg)
+    assert nvis > 500 and M >= nvis
+
+
+def test_small_forward(small):
+    scene, cam, cfg, _ = small
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    ref = O.render(scene, cam, cfg)
+    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref)
+    assert n_ok > 0.95 * cam.width * cam.height
+    print("small forward", n_ok, n_flag, worst)
+
+
+def test_small_backward(small):
+    scene, cam, cfg, seed = small
+    dC, _, _ = synth.upstream(seed, cam.width, cam.height)
+    ref_f = O.render(scene, cam, cfg)
+    dC = dC * (ref_f["flag"] == 0)[None]
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    g = G.gpu_backward(ras, st, sct, out, dC)
+    r = O.backward(scene, cam, cfg, dC)
+    print("small backward", G.assert_grads(g, r))
+
+
+# ---------------------------------------------------------------------------
+# 20k triangles, 256x256, SH-1, sigma in {0.25, 1, 4}; rgb, alpha, depth
+# upstream gradients
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sigma", [0.25, 1.0, 4.0])
+def test_grad_workload(sigma):
+    wl = synth.workload_grad(sigma)
+    scene, cam, cfg = wl.scene, wl.cameras[0], wl.config
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    _check_projection(st, scene, cam, cfg)
+    _check_bins(st, scene, cam, cfg)
+    ref_f = O.render(scene, cam, cfg)
+    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref_f)
+    dC, dA, dD = synth.upstream(wl.upstream_seed, cam.width, cam.height, True, True)
+    keep = (ref_f["flag"] == 0)
+    dC, dA, dD = dC * keep[None], dA * keep, dD * keep
+    g = G.gpu_backward(ras, st, sct, out, dC, dA, dD)
+    r = O.backward(scene, cam, cfg, dC, dA, dD)
+    print("grad workload", sigma, n_ok, n_flag, worst, G.assert_grads(g, r))
+
+
+# ---------------------------------------------------------------------------
+# 300k and 3M triangles at 1280x720 (and 1600x1040): sampled pixels
+# ---------------------------------------------------------------------------
+
+def _sampled(scene, cam, cfg, seed, n_pix=4096):
+    pix = synth.pixel_sample(seed, cam.width, cam.height, n_pix)
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    ref = O.render(scene, cam, cfg, pix=pix)
+    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref, pix=pix)
+    dC, _, _ = synth.upstream(seed + 1000, cam.width, cam.height)
+    dCs = dC.reshape(3, -1)[:, pix] * (ref["flag"] == 0)[None]
+    full = np.zeros_like(dC).reshape(3, -1)
+    full[:, pix] = dCs
+    g = G.gpu_backward(ras, st, sct, out, full.reshape(dC.shape))
+    r = O.backward(scene, cam, cfg, dCs, pix=pix)
+    s = G.assert_grads(g, r)
+    return st, n_ok, n_flag, worst, s
+
+
+def test_mid_workload_sampled():
+    wl = synth.workload_mid()
+    st, n_ok, n_flag, worst, s = _sampled(wl.scene, wl.cameras[0], wl.config, 7)
+    print("mid", st.M, st.N_v, n_ok, n_flag, worst, s)
+
+
+@pytest.mark.parametrize("view", [0, 1])
+def test_large_workload_sampled(view):
+    wl = synth.workload_large()
+    cam = wl.cameras[view]
+    st, n_ok, n_flag, worst, s = _sampled(wl.scene, cam, wl.config, 11 + view)
+    print("large", view, cam.width, cam.height, st.M, st.N_v, n_ok, n_flag, worst, s)
+
+
+def test_mid_bins_bit_exact():
+    wl = synth.workload_mid()
+    scene, cam, cfg = wl.scene, wl.cameras[0], wl.config
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    _check_projection(st, scene, cam, cfg)
+    _check_bins(st, scene, cam, cfg)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H", [(1, 1), (17, 33), (100, 7), (255, 129)])
+def test_ragged_images(W, H):
+    sc, cam = random_soup(41, 300, W=W, H=H, size=0.8, deg=2)
+    cfg = Config(sh_degree=2, bg=(0.2, 0.1, 0.3))
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    _check_bins(st, sc, cam, cfg)
+    ref = O.render(sc, cam, cfg)
+    G.assert_forward(G.to_np(out), ref)
+    rng = np.random.default_rng(3)
+    dC = rng.normal(size=(3, H, W)) * (ref["flag"] == 0)[None]
+    g = G.gpu_backward(ras, st, sct, out, dC)
+    G.assert_grads(g, O.backward(sc, cam, cfg, dC))
+
+
+def test_deep_lists_and_termination():
+    """Thousands of large, overlapping triangles: tile lists longer than one
+    LDS batch, early termination, clamped opacities."""
+    sc, cam = random_soup(42, 3000, W=64, H=48, size=2.0, deg=0, sigma=(0.05, 2.0),
+                          o=(0.5, 1.0), zrange=(2.5, 6.0))
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    _check_bins(st, sc, cam, cfg)
+    r = st.ranges.cpu().numpy()
+    assert (r[:, 1] - r[:, 0]).max() > 256
+    ref = O.render(sc, cam, cfg)
+    assert (ref["T_final"] < 2e-4).mean() > 0.3
+    G.assert_forward(G.to_np(out), ref)
+    rng = np.random.default_rng(4)
+    dC = rng.normal(size=(3, 48, 64)) * (ref["flag"] == 0)[None]
+    g = G.gpu_backward(ras, st, sct, out, dC)
+    G.assert_grads(g, O.backward(sc, cam, cfg, dC))
+
+
+def test_empty_and_fully_culled():
+    cam = synth.identity_camera(40, 24)
+    cfg = Config(sh_degree=0)
+    empty = synth.Scene(np.zeros((0, 3, 3), np.float32), np.zeros(0, np.float32),
+                        np.zeros(0, np.float32), np.zeros((0, 1, 3), np.float32))
+    ras, st, sct, out = G.gpu_forward(empty, cam, cfg)
+    o = G.to_np(out)
+    assert st.M == 0 and np.all(o["alpha"] == 0) and np.all(o["T_final"] == 1)
+    behind = box = synth.box_soup(5, 50)
+    behind.v[:, :, 2] = -1.0                                  # all behind the camera
+    ras, st, sct, out = G.gpu_forward(behind, cam, cfg)
+    o = G.to_np(out)
+    assert st.M == 0 and st.N_v == 0 and np.all(o["rgb"] == 0)
+    g = G.gpu_backward(ras, st, sct, out, np.ones((3, 24, 40), np.float32))
+    assert all(np.all(x == 0) for x in g.values())
+
+
+def test_capacity_growth_and_device_count_mode():
+    """A too-small instance list is reported and grown (host-count mode);
+    in device-count mode the overflow flag is set on the device."""
+    sc, cam = random_soup(43, 400, W=64, H=64, size=1.5, deg=0)
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg, capacity=8)
+    assert st.capacity >= st.M > 8
+    _check_bins(st, sc, cam, cfg)
+    ras2, st2, sct2, out2 = G.gpu_forward(sc, cam, cfg, capacity=8, sync=False)
+    dc = st2.d_count.cpu().numpy()
+    assert dc[0] == st.M and dc[2] == 1
+    ras3, st3, sct3, out3 = G.gpu_forward(sc, cam, cfg, capacity=st.M, sync=False)
+    dc = st3.d_count.cpu().numpy()
+    assert dc[0] == st.M and dc[2] == 0
+    a, b = G.to_np(out), G.to_np(out3)
+    for k in ("rgb", "alpha", "depth", "T_final", "last"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_forward_deterministic():
+    wl = synth.workload_grad(1.0)
+    outs = [G.to_np(G.gpu_forward(wl.scene, wl.cameras[0], wl.config)[3]) for _ in range(2)]
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
+
+
+def test_abi_rejects_bad_arguments():
+    from paper_2505_19175_amd import binding as B
+    sc, cam = random_soup(44, 10, W=32, H=32)
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    bad_cfg = B.make_config(Config(sh_degree=7))
+    with pytest.raises(B.TSError) as e:
+        B.ts_project(*sct, sc.n, B.make_camera(cam), bad_cfg, st.proj)
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_bin_sort(st.proj, sc.n, B.make_camera(cam), st.ws, 16, st.bins)
+    assert e.value.code == B.TS_EWORKSPACE
+    big = synth.identity_camera(20000, 8)
+    with pytest.raises(B.TSError) as e:
+        B.ts_project(*sct, sc.n, B.make_camera(big), B.make_config(cfg), st.proj)
+    assert e.value.code == B.TS_EINVAL
