@@ -1,0 +1,182 @@
+#!/usr/bin/env python
+"""Benchmark of the triangle-splatting hot path on one MI355X.
+
+One step = ts_project -> ts_bin_sort -> ts_render_forward ->
+ts_raster_backward -> ts_project_backward on one view of the 3M-triangle
+workload (SH degree 3, 70% dense clusters + 30% background shell,
+1280x720 from the first hemisphere pose), inputs and the upstream image
+gradient resident in HBM.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--view 0|1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpixel/s @3M tris 1280×720; serve frames/s + p50/p99 ms vs plain"
+HBM_PEAK_GBS = 8000.0
+P_REC = 48      # minimum raster record: 2D vertices, o, sigma, rgb, z (bytes)
+G_REC = 48      # 2D gradient record (bytes)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(N, N_v, M, W, H, K, n_upstream=1):
+    """Bytes each stage must move at minimum (radix passes beyond one,
+    re-reads and atomic retries excluded)."""
+    sh = 12 * K
+    return {
+        "project": 44 * N + sh * N_v + P_REC * N_v,
+        "bin_sort": 36 * M,
+        "raster_fwd": P_REC * N_v + 4 * M + 28 * W * H,
+        "raster_bwd": 12 * n_upstream * W * H + 8 * W * H + 4 * M + P_REC * N_v + 2 * G_REC * N_v,
+        "project_bwd": (44 + sh) * N_v + G_REC * N_v + (44 + sh) * N,
+    }
+
+
+def cpu_baseline(wl, cam, n_pix, seed=2024):
+    from oracle import oracle as O
+    from paper_2505_19175_amd import synth
+    pix = synth.pixel_sample(seed, cam.width, cam.height, n_pix)
+    dC, _, _ = synth.upstream(seed + 1, cam.width, cam.height)
+    dCs = dC.reshape(3, -1)[:, pix]
+    t0 = time.perf_counter()
+    O.render(wl.scene, cam, wl.config, pix=pix)
+    O.backward(wl.scene, cam, wl.config, dCs, pix=pix)
+    dt = time.perf_counter() - t0
+    return {"value": round(n_pix / dt / 1e6, 6), "unit": "Mpixel/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{n_pix} seeded pixels of the same view, forward + backward "
+                      f"(FP64 brute force over all triangles), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--view", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2505_19175_amd import binding as B
+    from paper_2505_19175_amd import synth
+    from paper_2505_19175_amd.render import Rasterizer, ViewState, scene_to_device
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    wl = synth.workload_large()
+    cam = wl.cameras[args.view]
+    cfg = wl.config
+    K = (cfg.sh_degree + 1) ** 2
+    log(f"[bench] generated {wl.scene.n} triangles in {time.perf_counter() - t0:.1f}s")
+    scene_t = scene_to_device(wl.scene, dev)
+    W, H, N = cam.width, cam.height, wl.scene.n
+    dC_np, _, _ = synth.upstream(wl.upstream_seed, W, H)
+    dC = torch.tensor(dC_np, device=dev)
+
+    # size the instance list once with a host read-back, then run without one
+    ras = Rasterizer(cfg, device=dev)
+    st = ViewState(N, W, H, 4 * N, device=dev)
+    out = ras.forward(st, scene_t, cam, sync=True)
+    M, N_v = st.M, st.N_v
+    st._alloc_lists(int(M * 1.05) + 4096)
+    ccam = B.make_camera(cam)
+    ccfg = B.make_config(cfg)
+    v, o, sg, sh = scene_t
+    gv, go, gs, gsh = (torch.empty_like(t) for t in scene_t)
+    stream = torch.cuda.current_stream()
+    sh_ = stream.cuda_stream
+    log(f"[bench] N={N} N_v={N_v} M={M} {W}x{H}")
+
+    stages = ["project", "bin_sort", "raster_fwd", "raster_bwd", "project_bwd"]
+
+    def step(ev=None):
+        if ev: ev[0].record(stream)
+        B.ts_project(v, o, sg, sh, N, ccam, ccfg, st.proj, sh_)
+        if ev: ev[1].record(stream)
+        B.ts_bin_sort(st.proj, N, ccam, st.ws, st.ws_bytes, st.bins, None, sh_)
+        if ev: ev[2].record(stream)
+        B.ts_render_forward(st.proj, st.bins, ccam, ccfg, out.rgb, out.alpha, out.depth,
+                            out.T_final, out.last, sh_)
+        if ev: ev[3].record(stream)
+        B.ts_raster_backward(st.proj, st.bins, ccam, ccfg, dC, None, None, out.T_final, out.last,
+                             sh_)
+        if ev: ev[4].record(stream)
+        B.ts_project_backward(v, sh, N, st.proj, ccam, ccfg, gv, go, gs, gsh, sh_)
+        if ev: ev[5].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert int(st.d_count[2].item()) == 0, "instance list overflow"
+
+    # timed region: exactly K steps, per-stage events on the launch stream
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    per = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(5)]
+                    for k in range(args.steps)])           # ms
+    step_ms = float(per.sum(1).mean())
+    gpu_total_ms = float(evs[0][0].elapsed_time(evs[-1][5]))
+    ms_per_step = max(gpu_total_ms, wall * 1e3) / args.steps
+    stage_ms = {s: round(float(per[:, j].mean()), 4) for j, s in enumerate(stages)}
+
+    byt = algorithmic_bytes(N, N_v, M, W, H, K)
+    single_kernel = ["project", "raster_fwd", "raster_bwd", "project_bwd"]
+    dom = max(single_kernel, key=lambda s: stage_ms[s])
+    ach = byt[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}
+    total_bytes = sum(byt.values())
+    res = {
+        "metric": METRIC,
+        "value": round(W * H / (ms_per_step * 1e-3) / 1e6, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"tri3M_{W}x{H}: 3M triangles, SH degree 3, 70% in 64 dense "
+                               f"clusters + 30% on a radius-20 shell, hemisphere pose {args.view}",
+                   "N": N, "N_visible": N_v, "instances": M, "width": W, "height": H},
+        "triangles_per_s": round(N / (ms_per_step * 1e-3), 1),
+        "stage_ms": stage_ms,
+        "stage_GBps_algorithmic": {s: round(byt[s] / (stage_ms[s] * 1e-3) / 1e9, 1) for s in stages},
+        "step_hbm_frac": round(total_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a pixel sample")
+        res["cpu_baseline"] = cpu_baseline(wl, cam, args.cpu_pixels)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

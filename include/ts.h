@@ -179,6 +179,22 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
                        const uint32_t* last, float* gv, float* go, float* gsigma, float* gsh,
                        hipStream_t stream);
 
+/*
+ * The two halves of ts_render_backward, for callers that schedule them
+ * separately.  ts_raster_backward accumulates the per-triangle 2D gradients
+ * into proj->g2d (which must hold zeros for visible triangles, as
+ * ts_project and ts_project_backward leave it); ts_project_backward turns
+ * them into gv, go, gsigma, gsh and re-zeroes proj->g2d.
+ */
+int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                       const ts_config* cfg, const float* dL_drgb, const float* dL_dalpha,
+                       const float* dL_ddepth, const float* T_final, const uint32_t* last,
+                       hipStream_t stream);
+
+int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_proj* proj,
+                        const ts_camera* cam, const ts_config* cfg, float* gv, float* go,
+                        float* gsigma, float* gsh, hipStream_t stream);
+
 /* Static description of an error code. */
 const char* ts_error_string(int code);
 

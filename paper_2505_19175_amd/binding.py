@@ -23,8 +23,8 @@ TS_TILE = 16
 TS_G2D_STRIDE = 16
 
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
-           "ts_bin_sort", "ts_render_forward", "ts_render_backward", "ts_error_string",
-           "ts_last_error")
+           "ts_bin_sort", "ts_render_forward", "ts_render_backward", "ts_raster_backward",
+           "ts_project_backward", "ts_error_string", "ts_last_error")
 
 
 class TSError(RuntimeError):
@@ -85,6 +85,10 @@ def load():
     L.ts_render_forward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
     L.ts_render_backward.restype = ctypes.c_int
     L.ts_render_backward.argtypes = [P, P, P, P, I64, PP, PB, PC, PG, P, P, P, P, P, P, P, P, P, P]
+    L.ts_raster_backward.restype = ctypes.c_int
+    L.ts_raster_backward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
+    L.ts_project_backward.restype = ctypes.c_int
+    L.ts_project_backward.argtypes = [P, P, I64, PP, PC, PG, P, P, P, P, P]
     L.ts_error_string.restype = ctypes.c_char_p
     L.ts_error_string.argtypes = [ctypes.c_int]
     L.ts_last_error.restype = ctypes.c_char_p
@@ -154,6 +158,21 @@ def ts_render_backward(v, o, sigma, sh, N: int, proj: ts_proj, bins: ts_bins, ca
                                      _ptr(dL_ddepth), _ptr(T_final), _ptr(last), _ptr(gv),
                                      _ptr(go), _ptr(gsigma), _ptr(gsh), stream),
            "ts_render_backward")
+
+
+def ts_raster_backward(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config, dL_drgb,
+                       dL_dalpha, dL_ddepth, T_final, last, stream: int = 0):
+    _check(load().ts_raster_backward(ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(cam),
+                                     ctypes.byref(cfg), _ptr(dL_drgb), _ptr(dL_dalpha),
+                                     _ptr(dL_ddepth), _ptr(T_final), _ptr(last), stream),
+           "ts_raster_backward")
+
+
+def ts_project_backward(v, sh, N: int, proj: ts_proj, cam: ts_camera, cfg: ts_config, gv, go,
+                        gsigma, gsh, stream: int = 0):
+    _check(load().ts_project_backward(_ptr(v), _ptr(sh), N, ctypes.byref(proj), ctypes.byref(cam),
+                                      ctypes.byref(cfg), _ptr(gv), _ptr(go), _ptr(gsigma),
+                                      _ptr(gsh), stream), "ts_project_backward")
 
 
 def ts_error_string(code: int) -> str:

@@ -185,6 +185,40 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_backward");
 }
 
+int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                       const ts_config* cfg, const float* dL_drgb, const float* dL_dalpha,
+                       const float* dL_ddepth, const float* T_final, const uint32_t* last,
+                       hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_raster_backward: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_raster_backward: bad config");
+    if (!bins_ok(bins) || !proj_ok(proj)) return fail(TS_EINVAL, "ts_raster_backward: bad state");
+    if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_raster_backward: null upstream");
+    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, to_cam(cam), to_cfg(cfg),
+                               tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), dL_drgb,
+                               dL_dalpha, dL_ddepth, T_final, last, proj->g2d, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_raster_backward");
+}
+
+int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_proj* proj,
+                        const ts_camera* cam, const ts_config* cfg, float* gv, float* go,
+                        float* gsigma, float* gsh, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_project_backward: N out of range");
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_project_backward: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_project_backward: bad config");
+    if (N == 0) return TS_OK;
+    if (!proj_ok(proj) || !v || !sh || !gv || !go || !gsigma || !gsh)
+        return fail(TS_EINVAL, "ts_project_backward: null pointer");
+    ts::launch_backproject(v, sh, N, to_cam(cam), to_cfg(cfg), proj->rect, proj->ntiles,
+                           proj->g2d, gv, go, gsigma, gsh, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project_backward");
+}
+
 const char* ts_error_string(int code)
 {
     switch (code) {

@@ -19,7 +19,12 @@ from paper_2505_19175_amd import synth
 from paper_2505_19175_amd.synth import Config
 
 import gpu_util as G
-from helpers import random_soup
+from helpers import random_soup as _soup64
+
+
+def random_soup(*a, **k):
+    """The GPU reads float32: give the oracle the very same float32 values."""
+    return _soup64(*a, dtype=np.float32, **k)
 
 pytestmark = pytest.mark.gpu
 
