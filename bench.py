@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--view", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 512 MiB device to device (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
@@ -81,6 +83,13 @@ def main():
     from paper_2505_19175_amd.render import Rasterizer, ViewState, scene_to_device
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 4}))
+        return
     t0 = time.perf_counter()
     wl = synth.workload_large()
     cam = wl.cameras[args.view]

@@ -21,13 +21,36 @@ __device__ __forceinline__ bool quad_hit(const TriRecord& r, int qx0, int qy0)
     return r.px0 <= qx0 + 7 && r.px1 >= qx0 && r.py0 <= qy0 + 7 && r.py1 >= qy0;
 }
 
-__device__ __forceinline__ void stage(TriRecord* s_rec, const TriRecord* __restrict__ rec,
-                                      uint32_t tri)
+// Copy one record into LDS slot threadIdx.x and return the 4-bit mask of
+// the tile's 8x8 quadrants its tight box touches (bit w = quadrant of wave w).
+__device__ __forceinline__ uint32_t stage(TriRecord* s_rec, const TriRecord* __restrict__ rec,
+                                          uint32_t tri, int tx0, int ty0)
 {
     const float4* src = reinterpret_cast<const float4*>(rec + tri);
     float4* dst = reinterpret_cast<float4*>(s_rec + threadIdx.x);
+    float4 t[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) dst[j] = src[j];
+    for (int j = 0; j < 8; ++j) t[j] = src[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[j] = t[j];
+    const TriRecord& r = *reinterpret_cast<const TriRecord*>(t);
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        m |= quad_hit(r, tx0 + (w & 1) * 8, ty0 + (w >> 1) * 8) ? (1u << w) : 0u;
+    return m;
+}
+
+// Entries of the current batch whose box touches wave w's quadrant: one
+// 64-bit mask per 64 entries, from the per-entry masks written at staging.
+__device__ __forceinline__ void wave_hits(const uint8_t* s_hit, int n, int w, int lane,
+                                          uint64_t (&hits)[kBatch / 64])
+{
+#pragma unroll
+    for (int c = 0; c < kBatch / 64; ++c) {
+        const int j = c * 64 + lane;
+        hits[c] = __ballot(j < n && ((s_hit[j] >> w) & 1u));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -40,6 +63,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     float* __restrict__ out_T, uint32_t* __restrict__ out_last)
 {
     __shared__ TriRecord s_rec[kBatch];
+    __shared__ uint8_t s_hit[kBatch];
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -55,12 +79,17 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     for (uint32_t b = start; b < end; b += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b);
         __syncthreads();
-        if (tid < n) stage(s_rec, rec, vals[b + tid]);
+        if (tid < n) s_hit[tid] = (uint8_t)stage(s_rec, rec, vals[b + tid], tx * kTile, ty * kTile);
         __syncthreads();
-        if (__ballot(!done) != 0ull) {
-            for (int j = 0; j < n; ++j) {
+        uint64_t hits[kBatch / 64];
+        wave_hits(s_hit, n, w, lane, hits);
+        bool wave_done = __ballot(!done) == 0ull;
+        for (int c = 0; c < kBatch / 64 && !wave_done; ++c) {
+            uint64_t m = hits[c];
+            while (m != 0ull) {
+                const int j = c * 64 + __builtin_ctzll(m);
+                m &= m - 1ull;
                 const TriRecord& r = s_rec[j];
-                if (!quad_hit(r, qx0, qy0)) continue;
                 if (!done) {
                     int k;
                     const double u = edge_min(r.A, r.B, r.C, (double)(px - r.ax),
@@ -84,7 +113,10 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
                         }
                     }
                 }
-                if (__ballot(!done) == 0ull) break;
+                if (__ballot(!done) == 0ull) {
+                    wave_done = true;
+                    break;
+                }
             }
         }
         if (__syncthreads_and(done)) break;
@@ -155,6 +187,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
 {
     __shared__ TriRecord s_rec[kBatch];
     __shared__ uint32_t s_tri[kBatch];
+    __shared__ uint8_t s_hit[kBatch];
     __shared__ uint32_t s_max;
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -196,13 +229,18 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         if (tid < n) {
             const uint32_t tri = vals[start + lo_ + tid];
             s_tri[tid] = tri;
-            stage(s_rec, rec, tri);
+            s_hit[tid] = (uint8_t)stage(s_rec, rec, tri, tx * kTile, ty * kTile);
         }
         __syncthreads();
-        for (int j = n - 1; j >= 0; --j) {
+        uint64_t hits[kBatch / 64];
+        wave_hits(s_hit, n, w, lane, hits);
+        for (int c = kBatch / 64 - 1; c >= 0; --c) {
+          uint64_t m = hits[c];
+          while (m != 0ull) {
+            const int j = c * 64 + 63 - __builtin_clzll(m);   // back to front
+            m &= ~(1ull << (j - c * 64));
             const uint32_t idx = lo_ + (uint32_t)j;   // entry index within the tile
             const TriRecord& r = s_rec[j];
-            if (!quad_hit(r, qx0, qy0)) continue;
             bool contrib = false;
             float v[16];
 #pragma unroll
@@ -256,6 +294,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
                 if ((lane & 3) == 0 && (lane >> 2) < 15)
                     unsafeAtomicAdd(g2d + (int64_t)s_tri[j] * TS_G2D_STRIDE + (lane >> 2), tot);
             }
+          }
         }
         hi_ = lo_;
     }
