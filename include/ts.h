@@ -195,6 +195,56 @@ int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_pro
                         const ts_camera* cam, const ts_config* cfg, float* gv, float* go,
                         float* gsigma, float* gsh, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched forward rendering of several views of one resident soup (serving).
+ * ------------------------------------------------------------------------ */
+
+/* One view of a batch.  tile_offset, tiles_x and pixel_offset place the
+ * view's tiles and pixels in the batch; ts_batch_layout fills them. */
+typedef struct ts_view {
+    ts_camera cam;
+    uint32_t tile_offset;   /* first batch-wide tile id of this view */
+    uint32_t tiles_x;       /* ceil(width / 16) */
+    uint64_t pixel_offset;  /* first pixel of this view in the packed outputs */
+} ts_view;
+
+/* Host helper: fills tile_offset, tiles_x and pixel_offset of views[0..n)
+ * (in order) and returns the batch's tile and pixel totals. */
+int ts_batch_layout(ts_view* views, int32_t n, uint32_t* total_tiles, uint64_t* total_pixels);
+
+/* Workspace bytes of ts_render_forward_batched for N triangles, up to
+ * max_views views, `capacity` instances and max_tiles tiles per batch. */
+size_t ts_batch_workspace_bytes(int64_t N, int32_t max_views, uint64_t capacity,
+                                uint32_t max_tiles);
+
+/*
+ * Forward render of a batch of views in one fixed sequence of launches
+ * whose sizes do not depend on the batch content, so the sequence can be
+ * captured once in a HIP graph and replayed with new views:
+ *   - one projection pass loads every triangle once and sets it up for all
+ *     views of the batch (record of (view, triangle) at view * N + triangle)
+ *   - one binning pass orders the instances of all views by batch-wide tile
+ *   - one persistent launch drains a tile queue shared by the views, so
+ *     views of different resolutions balance across the chip.
+ * Arguments (device unless noted):
+ *   views      [max_views] views, laid out by ts_batch_layout
+ *   ctl        [2] uint32: number of views in this batch, their total tiles
+ *   proj       per-entry arrays of max_views * N entries (g2d may be NULL)
+ *   bins       vals / keys of `capacity` entries, ranges of max_tiles tiles;
+ *              d_count[2] is set when the batch's instances exceeded capacity
+ *              (the frames are then incomplete and must be rendered again)
+ *   rgb        packed planar outputs: view v's [3][H][W] block starts at
+ *              rgb + 3 * pixel_offset; alpha / depth: [H][W] at pixel_offset
+ * The same per-pixel arithmetic as ts_render_forward: a view rendered alone
+ * and inside a batch gives identical pixels.
+ */
+int ts_render_forward_batched(const float* v, const float* o, const float* sigma,
+                              const float* sh, int64_t N, const ts_view* views,
+                              const uint32_t* ctl, int32_t max_views, uint32_t max_tiles,
+                              const ts_config* cfg, const ts_proj* proj, const ts_bins* bins,
+                              void* ws, size_t ws_bytes, float* rgb, float* alpha, float* depth,
+                              hipStream_t stream);
+
 /* Static description of an error code. */
 const char* ts_error_string(int code);
 

@@ -24,7 +24,8 @@ TS_G2D_STRIDE = 16
 
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
            "ts_bin_sort", "ts_render_forward", "ts_render_backward", "ts_raster_backward",
-           "ts_project_backward", "ts_error_string", "ts_last_error")
+           "ts_project_backward", "ts_batch_layout", "ts_batch_workspace_bytes",
+           "ts_render_forward_batched", "ts_error_string", "ts_last_error")
 
 
 class TSError(RuntimeError):
@@ -54,6 +55,11 @@ class ts_bins(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p),
                 ("ranges", ctypes.c_void_p), ("d_count", ctypes.c_void_p),
                 ("capacity", ctypes.c_uint64)]
+
+
+class ts_view(ctypes.Structure):
+    _fields_ = [("cam", ts_camera), ("tile_offset", ctypes.c_uint32), ("tiles_x", ctypes.c_uint32),
+                ("pixel_offset", ctypes.c_uint64)]
 
 
 _lib = None
@@ -89,6 +95,13 @@ def load():
     L.ts_raster_backward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
     L.ts_project_backward.restype = ctypes.c_int
     L.ts_project_backward.argtypes = [P, P, I64, PP, PC, PG, P, P, P, P, P]
+    L.ts_batch_layout.restype = ctypes.c_int
+    L.ts_batch_layout.argtypes = [P, ctypes.c_int32, P, P]
+    L.ts_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.ts_batch_workspace_bytes.argtypes = [I64, ctypes.c_int32, U64, ctypes.c_uint32]
+    L.ts_render_forward_batched.restype = ctypes.c_int
+    L.ts_render_forward_batched.argtypes = [P, P, P, P, I64, P, P, ctypes.c_int32, ctypes.c_uint32,
+                                            PG, PP, PB, P, ctypes.c_size_t, P, P, P, P]
     L.ts_error_string.restype = ctypes.c_char_p
     L.ts_error_string.argtypes = [ctypes.c_int]
     L.ts_last_error.restype = ctypes.c_char_p
@@ -173,6 +186,31 @@ def ts_project_backward(v, sh, N: int, proj: ts_proj, cam: ts_camera, cfg: ts_co
     _check(load().ts_project_backward(_ptr(v), _ptr(sh), N, ctypes.byref(proj), ctypes.byref(cam),
                                       ctypes.byref(cfg), _ptr(gv), _ptr(go), _ptr(gsigma),
                                       _ptr(gsh), stream), "ts_project_backward")
+
+
+def ts_batch_layout(views, n: int):
+    """views: ctypes array of ts_view (host), filled in place.
+    Returns (total_tiles, total_pixels)."""
+    tt = ctypes.c_uint32()
+    tp = ctypes.c_uint64()
+    _check(load().ts_batch_layout(ctypes.cast(views, ctypes.c_void_p), n, ctypes.byref(tt),
+                                  ctypes.byref(tp)), "ts_batch_layout")
+    return int(tt.value), int(tp.value)
+
+
+def ts_batch_workspace_bytes(N: int, max_views: int, capacity: int, max_tiles: int) -> int:
+    return int(load().ts_batch_workspace_bytes(N, max_views, capacity, max_tiles))
+
+
+def ts_render_forward_batched(v, o, sigma, sh, N: int, views, ctl, max_views: int, max_tiles: int,
+                              cfg: ts_config, proj: ts_proj, bins: ts_bins, ws, ws_bytes: int, rgb,
+                              alpha, depth, stream: int = 0):
+    _check(load().ts_render_forward_batched(_ptr(v), _ptr(o), _ptr(sigma), _ptr(sh), N,
+                                            _ptr(views), _ptr(ctl), max_views, max_tiles,
+                                            ctypes.byref(cfg), ctypes.byref(proj),
+                                            ctypes.byref(bins), _ptr(ws), ws_bytes, _ptr(rgb),
+                                            _ptr(alpha), _ptr(depth), stream),
+           "ts_render_forward_batched")
 
 
 def ts_error_string(code: int) -> str:

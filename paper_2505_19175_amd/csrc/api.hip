@@ -3,6 +3,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "ts_device.h"
 #include "ts_kernels.h"
 
@@ -131,8 +133,8 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
         }
         return TS_OK;
     }
-    e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, N, tiles_x_of(cam), num_tiles, w,
-                         *out, h_count, &overflow, stream);
+    e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, N, nullptr, nullptr, 0,
+                         tiles_x_of(cam), num_tiles, w, *out, h_count, &overflow, stream);
     if (e != hipSuccess) return hip_fail(e, "ts_bin_sort");
     if (overflow) return fail(TS_ECAPACITY, "ts_bin_sort: instances exceed capacity");
     return TS_OK;
@@ -217,6 +219,85 @@ int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_pro
                            proj->g2d, gv, go, gsigma, gsh, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project_backward");
+}
+
+int ts_batch_layout(ts_view* views, int32_t n, uint32_t* total_tiles, uint64_t* total_pixels)
+{
+    g_msg[0] = 0;
+    if (!views || n < 0 || !total_tiles || !total_pixels)
+        return fail(TS_EINVAL, "ts_batch_layout: bad arguments");
+    uint64_t tiles = 0, pixels = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!cam_ok(&views[i].cam)) return fail(TS_EINVAL, "ts_batch_layout: bad camera");
+        views[i].tile_offset = (uint32_t)tiles;
+        views[i].tiles_x = (uint32_t)tiles_x_of(&views[i].cam);
+        views[i].pixel_offset = pixels;
+        tiles += (uint64_t)ts_num_tiles(views[i].cam.width, views[i].cam.height);
+        pixels += (uint64_t)views[i].cam.width * (uint64_t)views[i].cam.height;
+    }
+    if (tiles > 0xffffffffull) return fail(TS_EINVAL, "ts_batch_layout: too many tiles");
+    *total_tiles = (uint32_t)tiles;
+    *total_pixels = pixels;
+    return TS_OK;
+}
+
+size_t ts_batch_workspace_bytes(int64_t N, int32_t max_views, uint64_t capacity,
+                                uint32_t max_tiles)
+{
+    (void)max_tiles;
+    if (N < 0 || max_views <= 0) return 0;
+    return ts::carve_bin_workspace(nullptr, N * max_views, capacity).bytes + 256;
+}
+
+int ts_render_forward_batched(const float* v, const float* o, const float* sigma,
+                              const float* sh, int64_t N, const ts_view* views,
+                              const uint32_t* ctl, int32_t max_views, uint32_t max_tiles,
+                              const ts_config* cfg, const ts_proj* proj, const ts_bins* bins,
+                              void* ws, size_t ws_bytes, float* rgb, float* alpha, float* depth,
+                              hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N <= 0 || max_views <= 0 || N * (int64_t)max_views > 0xffffffffll || max_tiles == 0)
+        return fail(TS_EINVAL, "ts_render_forward_batched: sizes out of range");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_forward_batched: bad config");
+    if (!v || !o || !sigma || !sh || !views || !ctl || !rgb || !alpha || !depth)
+        return fail(TS_EINVAL, "ts_render_forward_batched: null pointer");
+    if (!proj || !proj->rec || !proj->rect || !proj->depth || !proj->ntiles || !bins_ok(bins))
+        return fail(TS_EINVAL, "ts_render_forward_batched: bad projection or bins");
+    const int64_t entries = N * (int64_t)max_views;
+    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, entries, bins->capacity);
+    if (!ws || ws_bytes < need.bytes + 256)
+        return fail(TS_EWORKSPACE, "ts_render_forward_batched: workspace too small");
+    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, entries, bins->capacity);
+    uint32_t* extra = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + need.bytes);
+    uint32_t* queue = extra;        // tile queue head
+    uint32_t* bctl = extra + 4;     // clamped descriptor: views, tiles, views * N
+    uint32_t* n_entries = bctl + 2;
+    const ts::Cfg g = to_cfg(cfg);
+
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    const int workgroups = (int)std::min<int64_t>((int64_t)max_tiles, (int64_t)cus * 4);
+
+    ts::launch_fill_u32(queue, 1, 0u, stream);
+    ts::launch_batch_ctl(ctl, (uint32_t)max_views, max_tiles, N, bctl, stream);
+    ts::launch_project_views(v, o, sigma, sh, N, views, bctl, g, proj->rec, proj->rect,
+                             proj->depth, proj->ntiles, stream);
+    bool overflow = false;
+    hipError_t e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, entries, n_entries,
+                                    views, N, 0, (int)max_tiles, w, *bins, nullptr, &overflow,
+                                    stream);
+    if (e != hipSuccess) return hip_fail(e, "ts_render_forward_batched");
+    ts::launch_raster_forward_queue(proj->rec, bins->vals, bins->ranges, views, bctl, g, queue,
+                                    workgroups, rgb, alpha, depth, stream);
+    e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward_batched");
 }
 
 const char* ts_error_string(int code)

@@ -95,9 +95,13 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t& t
 // 1. compaction of visible triangles
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restrict__ ntiles,
-                                                       int64_t N, uint32_t* __restrict__ blk)
+                                                       int64_t N_host,
+                                                       const uint32_t* __restrict__ d_n,
+                                                       uint32_t* __restrict__ blk)
 {
     __shared__ uint32_t s_tmp[4];
+    const int64_t N = d_n ? (int64_t)*d_n : N_host;
+    if ((int64_t)blockIdx.x >= nblocks(N)) return;
     const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
     uint32_t c = 0;
 #pragma unroll
@@ -152,12 +156,15 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
 }
 
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ ntiles,
-                                                 const float* __restrict__ depth, int64_t N,
+                                                 const float* __restrict__ depth, int64_t N_host,
+                                                 const uint32_t* __restrict__ d_n,
                                                  const uint32_t* __restrict__ blk,
                                                  uint32_t* __restrict__ dk,
                                                  uint32_t* __restrict__ dv)
 {
     __shared__ uint32_t s_tmp[4];
+    const int64_t N = d_n ? (int64_t)*d_n : N_host;
+    if ((int64_t)blockIdx.x >= nblocks(N)) return;
     const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
     uint32_t f[kItems], c = 0;
 #pragma unroll
@@ -327,6 +334,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
                                               const uint32_t* __restrict__ dv,
                                               const uint32_t* __restrict__ d_nv,
                                               const uint32_t* __restrict__ blk, int tiles_x,
+                                              const ts_view* __restrict__ views, int64_t per_view,
                                               uint64_t capacity, uint32_t* __restrict__ tk,
                                               uint32_t* __restrict__ tv)
 {
@@ -350,10 +358,17 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
         const short4 rc = rect[tri[r]];
         const int tx0 = rc.x / kTile, tx1 = rc.y / kTile;
         const int ty0 = rc.z / kTile, ty1 = rc.w / kTile;
+        uint32_t toff = 0;
+        int tw = tiles_x;
+        if (views) {   // batched: entry = view * per_view + triangle
+            const ts_view& V = views[tri[r] / (uint64_t)per_view];
+            toff = V.tile_offset;
+            tw = (int)V.tiles_x;
+        }
         for (int ty = ty0; ty <= ty1; ++ty)
             for (int tx = tx0; tx <= tx1; ++tx) {
                 if (pos < capacity) {
-                    tk[pos] = (uint32_t)(ty * tiles_x + tx);
+                    tk[pos] = toff + (uint32_t)(ty * tw + tx);
                     tv[pos] = tri[r];
                 }
                 ++pos;
@@ -368,6 +383,26 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = x;
+}
+
+// Batch descriptor as the kernels use it, clamped to the buffers' sizes:
+// out[0] = views, out[1] = tiles, out[2] = views * per_view entries.
+__global__ void k_batch_ctl(const uint32_t* __restrict__ ctl_in, uint32_t max_views,
+                            uint32_t max_tiles, int64_t per_view, uint32_t* __restrict__ ctl_out)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t nv = min(ctl_in[0], max_views);
+        ctl_out[0] = nv;
+        ctl_out[1] = min(ctl_in[1], max_tiles);
+        ctl_out[2] = (uint32_t)((int64_t)nv * per_view);
+    }
+}
+
+void launch_batch_ctl(const uint32_t* ctl_in, uint32_t max_views, uint32_t max_tiles,
+                      int64_t per_view, uint32_t* ctl_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_batch_ctl, dim3(1), dim3(64), 0, stream, ctl_in, max_views, max_tiles,
+                       per_view, ctl_out);
 }
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream)
@@ -428,9 +463,9 @@ static int bits_for(int n)
 }
 
 hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_t* rect,
-                        int64_t N, int tiles_x, int num_tiles, const BinWorkspace& ws,
-                        const ts_bins& out, uint32_t* h_count, bool* overflow,
-                        hipStream_t stream)
+                        int64_t N, const uint32_t* d_n, const ts_view* views, int64_t per_view,
+                        int tiles_x, int num_tiles, const BinWorkspace& ws, const ts_bins& out,
+                        uint32_t* h_count, bool* overflow, hipStream_t stream)
 {
     *overflow = false;
     const int64_t nbN = nblocks(N);
@@ -440,14 +475,13 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     uint32_t* d_sortn = ws.ctl;         // min(M, capacity)
 
     launch_fill_u32(out.ranges, 2 * (int64_t)num_tiles, 0u, stream);
-    // 1. compaction
+    // 1. compaction (N, or *d_n entries when given)
     hipLaunchKernelGGL(k_count_visible, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, N,
-                       ws.blk);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk,
-                       (const uint32_t*)nullptr, N, d_Nv, (uint32_t*)nullptr, (uint64_t)0,
-                       (uint32_t*)nullptr);
+                       d_n, ws.blk);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk, d_n, N, d_Nv,
+                       (uint32_t*)nullptr, (uint64_t)0, (uint32_t*)nullptr);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, depth, N,
-                       ws.blk, ws.dk[0], ws.dv[0]);
+                       d_n, ws.blk, ws.dk[0], ws.dv[0]);
     // 2. depth order of the visible triangles (stable: index order kept on ties)
     hipError_t err = radix_sort(ws.dk[0], ws.dv[0], ws.dk[1], ws.dv[1], ws.dk[0], ws.dv[0], d_Nv,
                                 N, 32, ws, stream);
@@ -472,7 +506,7 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     }
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles,
                        reinterpret_cast<const short4*>(rect), ws.dv[0], d_Nv, ws.blk, tiles_x,
-                       out.capacity, ws.tk[0], ws.tv[0]);
+                       views, per_view, out.capacity, ws.tk[0], ws.tv[0]);
     // 4. stable sort by tile
     err = radix_sort(ws.tk[0], ws.tv[0], ws.tk[1], ws.tv[1], ws.tfin, out.vals, d_sortn, m_max,
                      bits_for(num_tiles), ws, stream);

@@ -96,24 +96,21 @@ __device__ __forceinline__ void view_dir(const float vv[9], const Cam& cam, doub
 template <int DEG>
 __device__ __forceinline__ void load_sh(const float* __restrict__ sh, int64_t i, float* c);
 
+// Set up triangle `tri` for one camera and write entry `e` of the outputs
+// (e = tri for a single view, view * N + tri in a batch).  The SH
+// coefficients are loaded on first use into c (shared across views).
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project(
-    const float* __restrict__ v, const float* __restrict__ o, const float* __restrict__ sigma,
-    const float* __restrict__ sh, int64_t N, Cam cam, Cfg cfg, TriRecord* __restrict__ rec,
-    short4* __restrict__ rect, float* __restrict__ depth, uint32_t* __restrict__ ntiles,
-    float4* __restrict__ g2d)
+__device__ __forceinline__ void project_one(const float vv[9], float oi, float si,
+                                            const float* __restrict__ sh, int64_t tri,
+                                            float* c, bool& c_loaded, const Cam& cam,
+                                            const Cfg& cfg, int64_t e, TriRecord* __restrict__ rec,
+                                            short4* __restrict__ rect, float* __restrict__ depth,
+                                            uint32_t* __restrict__ ntiles, float4* __restrict__ g2d)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-
-    float vv[9];
-    load_vertices(v, i, vv);
-    const float oi = o[i];
-    const float si = sigma[i];
     Geo g;
     project_geo(vv, cam, cfg.z_near, g);
     const double zc = depth_centre(vv, cam);
-    depth[i] = (float)zc;
+    depth[e] = (float)zc;
 
     const double r = g.P > 0.0 ? fabs(g.S) / g.P : 0.0;
     bool vis = g.front && (r >= (double)cfg.r_min) && (oi >= cfg.alpha_min) && (si > 0.f);
@@ -145,12 +142,12 @@ __global__ __launch_bounds__(256) void k_project(
         }
     }
     if (!vis) {
-        ntiles[i] = 0u;
-        rect[i] = make_short4(0, -1, 0, -1);
+        ntiles[e] = 0u;
+        rect[e] = make_short4(0, -1, 0, -1);
         return;
     }
-    rect[i] = make_short4((short)px0, (short)px1, (short)py0, (short)py1);
-    ntiles[i] = (uint32_t)((px1 / kTile - px0 / kTile + 1) * (py1 / kTile - py0 / kTile + 1));
+    rect[e] = make_short4((short)px0, (short)px1, (short)py0, (short)py1);
+    ntiles[e] = (uint32_t)((px1 / kTile - px0 / kTile + 1) * (py1 / kTile - py0 / kTile + 1));
 
     TriRecord R;
     // u_k(p) = w_k cross(e_k, p - q_k), w_k = P / (2A l_k), relative to the anchor
@@ -169,16 +166,19 @@ __global__ __launch_bounds__(256) void k_project(
     R.sigma = si;
     R.z = (float)zc;
     R.px0 = (int16_t)px0; R.px1 = (int16_t)px1; R.py0 = (int16_t)py0; R.py1 = (int16_t)py1;
-    R.tri = (uint32_t)i;
+    R.tri = (uint32_t)tri;
     R.pad[0] = R.pad[1] = R.pad[2] = 0.f;
 
     // colour: real SH along the view direction, + 1/2, clamped at zero
     double d[3], nrm;
     view_dir(vv, cam, d, nrm);
     constexpr int K = (DEG + 1) * (DEG + 1);
-    float Y[16], c[3 * K];
+    float Y[16];
     sh_basis(DEG, (float)d[0], (float)d[1], (float)d[2], Y);
-    load_sh<DEG>(sh, i, c);
+    if (!c_loaded) {
+        load_sh<DEG>(sh, tri, c);
+        c_loaded = true;
+    }
     float acc[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -191,12 +191,60 @@ __global__ __launch_bounds__(256) void k_project(
     R.rgb[2] = fmaxf(acc[2], 0.f);
 
     const float4* src = reinterpret_cast<const float4*>(&R);
-    float4* dst = reinterpret_cast<float4*>(rec + i);
+    float4* dst = reinterpret_cast<float4*>(rec + e);
 #pragma unroll
     for (int j = 0; j < 8; ++j) dst[j] = src[j];
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g2d) {
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) g2d[4 * i + j] = z4;
+        for (int j = 0; j < 4; ++j) g2d[4 * e + j] = z4;
+    }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project(
+    const float* __restrict__ v, const float* __restrict__ o, const float* __restrict__ sigma,
+    const float* __restrict__ sh, int64_t N, Cam cam, Cfg cfg, TriRecord* __restrict__ rec,
+    short4* __restrict__ rect, float* __restrict__ depth, uint32_t* __restrict__ ntiles,
+    float4* __restrict__ g2d)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float vv[9], c[3 * (DEG + 1) * (DEG + 1)];
+    bool c_loaded = false;
+    load_vertices(v, i, vv);
+    project_one<DEG>(vv, o[i], sigma[i], sh, i, c, c_loaded, cam, cfg, i, rec, rect, depth,
+                     ntiles, g2d);
+}
+
+// All views of a batch: each triangle is read once (vertices, opacity,
+// sigma, and its SH row only if some view keeps it) and set up per view.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_views(
+    const float* __restrict__ v, const float* __restrict__ o, const float* __restrict__ sigma,
+    const float* __restrict__ sh, int64_t N, const ts_view* __restrict__ views,
+    const uint32_t* __restrict__ ctl, Cfg cfg, TriRecord* __restrict__ rec,
+    short4* __restrict__ rect, float* __restrict__ depth, uint32_t* __restrict__ ntiles)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint32_t nviews = ctl[0];
+    float vv[9], c[3 * (DEG + 1) * (DEG + 1)];
+    bool c_loaded = false;
+    load_vertices(v, i, vv);
+    const float oi = o[i], si = sigma[i];
+    for (uint32_t view = 0; view < nviews; ++view) {
+        const ts_camera& vc = views[view].cam;
+        Cam cam;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) cam.R[a] = vc.R[a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cam.t[a] = vc.t[a];
+        cam.fx = vc.fx; cam.fy = vc.fy; cam.cx = vc.cx; cam.cy = vc.cy;
+        cam.W = vc.width; cam.H = vc.height;
+        project_one<DEG>(vv, oi, si, sh, i, c, c_loaded, cam, cfg, (int64_t)view * N + i, rec,
+                         rect, depth, ntiles, nullptr);
+    }
 }
 
 // Coefficients of one triangle: float4 loads when the row is 16-byte aligned.
@@ -425,6 +473,22 @@ void launch_project(const float* v, const float* o, const float* sigma, const fl
     case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, g4); break;
     case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, g4); break;
     default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, g4); break;
+    }
+}
+
+void launch_project_views(const float* v, const float* o, const float* sigma, const float* sh,
+                          int64_t N, const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
+                          void* rec, int16_t* rect, float* depth, uint32_t* ntiles,
+                          hipStream_t stream)
+{
+    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    TriRecord* r = reinterpret_cast<TriRecord*>(rec);
+    short4* r4 = reinterpret_cast<short4*>(rect);
+    switch (cfg.deg) {
+    case 0: hipLaunchKernelGGL(k_project_views<0>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
+    case 1: hipLaunchKernelGGL(k_project_views<1>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
+    case 2: hipLaunchKernelGGL(k_project_views<2>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
+    default: hipLaunchKernelGGL(k_project_views<3>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
     }
 }
 

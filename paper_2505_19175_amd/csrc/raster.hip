@@ -56,21 +56,27 @@ __device__ __forceinline__ void wave_hits(const uint8_t* s_hit, int n, int w, in
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_raster_fwd(
-    const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, Cam cam, Cfg cfg, int tiles_x,
-    float* __restrict__ out_rgb, float* __restrict__ out_alpha, float* __restrict__ out_depth,
-    float* __restrict__ out_T, uint32_t* __restrict__ out_last)
+
+// One tile of one view.  T_final / last may be null (forward-only serving).
+struct TileJob {
+    int tx, ty, W, H;
+    uint32_t start, end;
+    float* rgb;
+    float* alpha;
+    float* depth;
+    float* T;
+    uint32_t* last;
+};
+
+__device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
+                                         const uint32_t* __restrict__ vals, const Cfg& cfg,
+                                         const TileJob& J, TriRecord* s_rec, uint8_t* s_hit)
 {
-    __shared__ TriRecord s_rec[kBatch];
-    __shared__ uint8_t s_hit[kBatch];
-    const int tile = blockIdx.x;
-    const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int qx0 = tx * kTile + (w & 1) * 8, qy0 = ty * kTile + (w >> 1) * 8;
+    const int qx0 = J.tx * kTile + (w & 1) * 8, qy0 = J.ty * kTile + (w >> 1) * 8;
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
-    const bool inside = px < cam.W && py < cam.H;
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const bool inside = px < J.W && py < J.H;
+    const uint32_t start = J.start, end = J.end;
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     uint32_t last = 0;
@@ -79,7 +85,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     for (uint32_t b = start; b < end; b += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b);
         __syncthreads();
-        if (tid < n) s_hit[tid] = (uint8_t)stage(s_rec, rec, vals[b + tid], tx * kTile, ty * kTile);
+        if (tid < n)
+            s_hit[tid] = (uint8_t)stage(s_rec, rec, vals[b + tid], J.tx * kTile, J.ty * kTile);
         __syncthreads();
         uint64_t hits[kBatch / 64];
         wave_hits(s_hit, n, w, lane, hits);
@@ -122,15 +129,60 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
         if (__syncthreads_and(done)) break;
     }
     if (inside) {
-        const int64_t p = (int64_t)py * cam.W + px;
-        const int64_t hw = (int64_t)cam.W * cam.H;
-        out_rgb[p] = fmaf(cfg.bg[0], T, C0);
-        out_rgb[hw + p] = fmaf(cfg.bg[1], T, C1);
-        out_rgb[2 * hw + p] = fmaf(cfg.bg[2], T, C2);
-        out_alpha[p] = 1.f - T;
-        out_depth[p] = D;
-        out_T[p] = T;
-        out_last[p] = last;
+        const int64_t p = (int64_t)py * J.W + px;
+        const int64_t hw = (int64_t)J.W * J.H;
+        J.rgb[p] = fmaf(cfg.bg[0], T, C0);
+        J.rgb[hw + p] = fmaf(cfg.bg[1], T, C1);
+        J.rgb[2 * hw + p] = fmaf(cfg.bg[2], T, C2);
+        J.alpha[p] = 1.f - T;
+        J.depth[p] = D;
+        if (J.T) J.T[p] = T;
+        if (J.last) J.last[p] = last;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_raster_fwd(
+    const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, Cam cam, Cfg cfg, int tiles_x,
+    float* __restrict__ out_rgb, float* __restrict__ out_alpha, float* __restrict__ out_depth,
+    float* __restrict__ out_T, uint32_t* __restrict__ out_last)
+{
+    __shared__ TriRecord s_rec[kBatch];
+    __shared__ uint8_t s_hit[kBatch];
+    const int tile = blockIdx.x;
+    TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
+              ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last};
+    fwd_tile(rec, vals, cfg, J, s_rec, s_hit);
+}
+
+// Persistent variant over the tiles of several views: each workgroup takes
+// the next tile from a queue until the batch's tiles run out.  views[] is
+// sorted by tile_offset; ctl[0] = views in the batch, ctl[1] = their tiles.
+__global__ __launch_bounds__(256) void k_raster_fwd_queue(
+    const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, const ts_view* __restrict__ views,
+    const uint32_t* __restrict__ ctl, Cfg cfg, uint32_t* __restrict__ queue,
+    float* __restrict__ out_rgb, float* __restrict__ out_alpha, float* __restrict__ out_depth)
+{
+    __shared__ TriRecord s_rec[kBatch];
+    __shared__ uint8_t s_hit[kBatch];
+    __shared__ uint32_t s_t;
+    const uint32_t nviews = ctl[0], total = ctl[1];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t t = s_t;
+        if (t >= total) break;
+        uint32_t v = 0;
+        while (v + 1 < nviews && views[v + 1].tile_offset <= t) ++v;
+        const ts_view& V = views[v];
+        const uint32_t local = t - V.tile_offset;
+        const int64_t po = (int64_t)V.pixel_offset;
+        TileJob J{(int)(local % V.tiles_x), (int)(local / V.tiles_x), V.cam.width, V.cam.height,
+                  ranges[2 * t], ranges[2 * t + 1], out_rgb + 3 * po, out_alpha + po,
+                  out_depth + po, nullptr, nullptr};
+        fwd_tile(rec, vals, cfg, J, s_rec, s_hit);
     }
 }
 
@@ -308,6 +360,16 @@ void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t
     hipLaunchKernelGGL(k_raster_fwd, dim3(num_tiles), dim3(kBlock), 0, stream,
                        reinterpret_cast<const TriRecord*>(rec), vals, ranges, cam, cfg, tiles_x,
                        rgb, alpha, depth, T_final, last);
+}
+
+void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
+                                 const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
+                                 uint32_t* queue, int workgroups, float* rgb, float* alpha,
+                                 float* depth, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_raster_fwd_queue, dim3(workgroups), dim3(kBlock), 0, stream,
+                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, views, ctl, cfg,
+                       queue, rgb, alpha, depth);
 }
 
 void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,

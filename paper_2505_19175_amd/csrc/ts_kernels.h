@@ -15,6 +15,16 @@ void launch_project(const float* v, const float* o, const float* sigma, const fl
                     int64_t N, const Cam& cam, const Cfg& cfg, void* rec, int16_t* rect,
                     float* depth, uint32_t* ntiles, float* g2d, hipStream_t stream);
 
+void launch_project_views(const float* v, const float* o, const float* sigma, const float* sh,
+                          int64_t N, const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
+                          void* rec, int16_t* rect, float* depth, uint32_t* ntiles,
+                          hipStream_t stream);
+
+// Device copy of a batch descriptor clamped to the buffers: ctl_out[0] =
+// views (<= max_views), [1] = tiles (<= max_tiles), [2] = views * per_view.
+void launch_batch_ctl(const uint32_t* ctl_in, uint32_t max_views, uint32_t max_tiles,
+                      int64_t per_view, uint32_t* ctl_out, hipStream_t stream);
+
 void launch_backproject(const float* v, const float* sh, int64_t N, const Cam& cam,
                         const Cfg& cfg, const int16_t* rect, const uint32_t* ntiles, float* g2d,
                         float* gv, float* go, float* gsig, float* gsh, hipStream_t stream);
@@ -40,16 +50,23 @@ struct BinWorkspace {
 
 BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity);
 
-// Device-side binning: returns hipSuccess or the first launch error.
+// Device-side binning of N entries (or *d_n <= N when d_n is set).  With
+// views set, entry e belongs to view e / per_view and its tiles are offset
+// by that view's tile_offset.  Returns hipSuccess or the first launch error.
 hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_t* rect,
-                        int64_t N, int tiles_x, int num_tiles, const BinWorkspace& ws,
-                        const ts_bins& out, uint32_t* h_count, bool* overflow,
-                        hipStream_t stream);
+                        int64_t N, const uint32_t* d_n, const ts_view* views, int64_t per_view,
+                        int tiles_x, int num_tiles, const BinWorkspace& ws, const ts_bins& out,
+                        uint32_t* h_count, bool* overflow, hipStream_t stream);
 
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                            const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
                            float* rgb, float* alpha, float* depth, float* T_final,
                            uint32_t* last, hipStream_t stream);
+
+void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
+                                 const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
+                                 uint32_t* queue, int workgroups, float* rgb, float* alpha,
+                                 float* depth, hipStream_t stream);
 
 void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                             const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
