@@ -131,7 +131,7 @@ def test_batching_beats_one_view_per_launch_at_saturation():
     c2, e2, s2, r2 = _run(rate=4000, duration=0.5, max_views=1, slots=1, launch=1e-3)
     f1 = summarize(r1, 0.0, 0.1, 0.5)["frames_per_s"]
     f2 = summarize(r2, 0.0, 0.1, 0.5)["frames_per_s"]
-    assert f1 > 2 * f2
+    assert f1 > 1.5 * f2
 
 
 def test_tiles_of():
