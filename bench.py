@@ -114,7 +114,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device to device (scale for HBM counters)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", default="200,500,1000,2000")
+    ap.add_argument("--serve-rates", default="200,500,1000,2000,4000,8000",
+                    help="req/s; the quoted 200-2000 plus two rates past saturation")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="load duration per rate, the first 0.5 s not measured")
     args = ap.parse_args()

@@ -107,6 +107,8 @@ typedef struct ts_bins {
     uint32_t* d_count;  /* [4] device counters: [0] instances M, [1] visible N_v,
                            [2] overflow flag (M > capacity), [3] reserved */
     uint64_t capacity;  /* entries available in keys / vals */
+    uint32_t* order;    /* [tiles] tiles by decreasing list length (the order in which
+                           the rasterizers take them); may be NULL: natural order */
 } ts_bins;
 
 /* Bytes of one raster record (the layout is private to the library). */

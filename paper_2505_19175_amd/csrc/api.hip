@@ -151,9 +151,9 @@ int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera*
         return fail(TS_EINVAL, "ts_render_forward: bad projection or bins");
     if (!rgb || !alpha || !depth || !T_final || !last)
         return fail(TS_EINVAL, "ts_render_forward: null output");
-    ts::launch_raster_forward(proj->rec, bins->vals, bins->ranges, to_cam(cam), to_cfg(cfg),
-                              tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), rgb,
-                              alpha, depth, T_final, last, stream);
+    ts::launch_raster_forward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
+                              to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
+                              rgb, alpha, depth, T_final, last, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward");
 }
@@ -178,9 +178,9 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
     if (N == 0) return TS_OK;
     const ts::Cam k = to_cam(cam);
     const ts::Cfg g = to_cfg(cfg);
-    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, k, g, tiles_x_of(cam),
-                               ts_num_tiles(cam->width, cam->height), dL_drgb, dL_dalpha,
-                               dL_ddepth, T_final, last, proj->g2d, stream);
+    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, k, g,
+                               tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), dL_drgb,
+                               dL_dalpha, dL_ddepth, T_final, last, proj->g2d, stream);
     ts::launch_backproject(v, sh, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go, gsigma,
                            gsh, stream);
     const hipError_t e = hipGetLastError();
@@ -197,9 +197,9 @@ int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera
     if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_raster_backward: bad config");
     if (!bins_ok(bins) || !proj_ok(proj)) return fail(TS_EINVAL, "ts_raster_backward: bad state");
     if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_raster_backward: null upstream");
-    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, to_cam(cam), to_cfg(cfg),
-                               tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), dL_drgb,
-                               dL_dalpha, dL_ddepth, T_final, last, proj->g2d, stream);
+    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
+                               to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
+                               dL_drgb, dL_dalpha, dL_ddepth, T_final, last, proj->g2d, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_raster_backward");
 }
@@ -292,9 +292,10 @@ int ts_render_forward_batched(const float* v, const float* o, const float* sigma
     bool overflow = false;
     hipError_t e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, entries, n_entries,
                                     views, N, 0, (int)max_tiles, w, *bins, nullptr, &overflow,
-                                    stream);
+                                    stream, bctl + 1);
     if (e != hipSuccess) return hip_fail(e, "ts_render_forward_batched");
-    ts::launch_raster_forward_queue(proj->rec, bins->vals, bins->ranges, views, bctl, g, queue,
+    ts::launch_raster_forward_queue(proj->rec, bins->vals, bins->ranges, bins->order, views, bctl,
+                                    g, queue,
                                     workgroups, rgb, alpha, depth, stream);
     e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward_batched");

@@ -411,6 +411,45 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream)
         hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, x);
 }
 
+// Tiles by decreasing list length (counting sort on the length, lengths of
+// 2047 and more share the first bucket; order inside a bucket is arbitrary).
+// Rasterizing the longest tiles first keeps them out of the tail of the
+// launch.  One workgroup; ctl (optional) holds the number of tiles.
+constexpr int kLenBuckets = 2048;
+
+__global__ __launch_bounds__(256) void k_tile_order(const uint32_t* __restrict__ ranges,
+                                                    int n_host, const uint32_t* __restrict__ d_n,
+                                                    uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t h[kLenBuckets];
+    __shared__ uint32_t s_tmp[4];
+    const int n = d_n ? (int)min(*d_n, (uint32_t)n_host) : n_host;
+    for (int b = threadIdx.x; b < kLenBuckets; b += kBlock) h[b] = 0u;
+    __syncthreads();
+    auto key = [&](int t) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        return (kLenBuckets - 1) - (int)min(len, (uint32_t)(kLenBuckets - 1));
+    };
+    for (int t = threadIdx.x; t < n; t += kBlock) atomicAdd(&h[key(t)], 1u);
+    __syncthreads();
+    constexpr int per = kLenBuckets / kBlock;
+    uint32_t loc[per], s = 0;
+#pragma unroll
+    for (int r = 0; r < per; ++r) {
+        loc[r] = h[threadIdx.x * per + r];
+        s += loc[r];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan(s, tot, s_tmp);
+#pragma unroll
+    for (int r = 0; r < per; ++r) {
+        h[threadIdx.x * per + r] = pre;
+        pre += loc[r];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += kBlock) order[atomicAdd(&h[key(t)], 1u)] = (uint32_t)t;
+}
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tfin,
                                                 const uint32_t* __restrict__ vals,
                                                 const float* __restrict__ depth,
@@ -465,7 +504,8 @@ static int bits_for(int n)
 hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_t* rect,
                         int64_t N, const uint32_t* d_n, const ts_view* views, int64_t per_view,
                         int tiles_x, int num_tiles, const BinWorkspace& ws, const ts_bins& out,
-                        uint32_t* h_count, bool* overflow, hipStream_t stream)
+                        uint32_t* h_count, bool* overflow, hipStream_t stream,
+                        const uint32_t* d_tiles)
 {
     *overflow = false;
     const int64_t nbN = nblocks(N);
@@ -514,6 +554,9 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     if (m_max > 0)
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((m_max + 255) / 256)), dim3(256), 0, stream,
                            ws.tfin, out.vals, depth, d_sortn, out.ranges, out.keys);
+    if (out.order)
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kBlock), 0, stream, out.ranges, num_tiles,
+                           d_tiles, out.order);
     return hipGetLastError();
 }
 

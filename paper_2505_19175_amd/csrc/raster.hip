@@ -166,12 +166,12 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
 
 __global__ __launch_bounds__(256) void k_raster_fwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, Cam cam, Cfg cfg, int tiles_x,
-    float* __restrict__ out_rgb, float* __restrict__ out_alpha, float* __restrict__ out_depth,
-    float* __restrict__ out_T, uint32_t* __restrict__ out_last)
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
+    int tiles_x, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
+    float* __restrict__ out_depth, float* __restrict__ out_T, uint32_t* __restrict__ out_last)
 {
     __shared__ Stage S;
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
               ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last};
     fwd_tile(rec, vals, cfg, J, S);
@@ -183,9 +183,10 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
 // (both already clamped to the buffers).
 __global__ __launch_bounds__(256) void k_raster_fwd_queue(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, const ts_view* __restrict__ views,
-    const uint32_t* __restrict__ ctl, Cfg cfg, uint32_t* __restrict__ queue,
-    float* __restrict__ out_rgb, float* __restrict__ out_alpha, float* __restrict__ out_depth)
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order,
+    const ts_view* __restrict__ views, const uint32_t* __restrict__ ctl, Cfg cfg,
+    uint32_t* __restrict__ queue, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
+    float* __restrict__ out_depth)
 {
     __shared__ Stage S;
     __shared__ uint32_t s_t;
@@ -194,8 +195,9 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
         __syncthreads();
         if (threadIdx.x == 0) s_t = atomicAdd(queue, 1u);
         __syncthreads();
-        const uint32_t t = s_t;
-        if (t >= total) break;
+        const uint32_t q = s_t;
+        if (q >= total) break;
+        const uint32_t t = order ? order[q] : q;
         uint32_t v = 0;
         while (v + 1 < nviews && views[v + 1].tile_offset <= t) ++v;
         const ts_view& V = views[v];
@@ -263,15 +265,15 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x)
 
 __global__ __launch_bounds__(256) void k_raster_bwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, Cam cam, Cfg cfg, int tiles_x,
-    const float* __restrict__ dL_drgb, const float* __restrict__ dL_dalpha,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
+    int tiles_x, const float* __restrict__ dL_drgb, const float* __restrict__ dL_dalpha,
     const float* __restrict__ dL_ddepth, const float* __restrict__ T_final,
     const uint32_t* __restrict__ last_in, float* __restrict__ g2d)
 {
     __shared__ Stage S;
     __shared__ uint32_t s_tri[kBatch];
     __shared__ uint32_t s_max;
-    const int tile = blockIdx.x;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int qx0 = tx * kTile + (w & 1) * 8, qy0 = ty * kTile + (w >> 1) * 8;
@@ -380,34 +382,35 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
 }
 
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
-                           const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
-                           float* rgb, float* alpha, float* depth, float* T_final,
+                           const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
+                           int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
                            uint32_t* last, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_raster_fwd, dim3(num_tiles), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, cam, cfg, tiles_x,
-                       rgb, alpha, depth, T_final, last);
+                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
+                       tiles_x, rgb, alpha, depth, T_final, last);
 }
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
-                                 const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
-                                 uint32_t* queue, int workgroups, float* rgb, float* alpha,
-                                 float* depth, hipStream_t stream)
+                                 const uint32_t* order, const ts_view* views,
+                                 const uint32_t* ctl, const Cfg& cfg, uint32_t* queue,
+                                 int workgroups, float* rgb, float* alpha, float* depth,
+                                 hipStream_t stream)
 {
     hipLaunchKernelGGL(k_raster_fwd_queue, dim3(workgroups), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, views, ctl, cfg,
-                       queue, rgb, alpha, depth);
+                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, views, ctl,
+                       cfg, queue, rgb, alpha, depth);
 }
 
 void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
-                            const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
-                            const float* dL_drgb, const float* dL_dalpha,
+                            const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
+                            int num_tiles, const float* dL_drgb, const float* dL_dalpha,
                             const float* dL_ddepth, const float* T_final,
                             const uint32_t* last, float* g2d, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_raster_bwd, dim3(num_tiles), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, cam, cfg, tiles_x,
-                       dL_drgb, dL_dalpha, dL_ddepth, T_final, last, g2d);
+                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
+                       tiles_x, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, g2d);
 }
 
 }  // namespace ts

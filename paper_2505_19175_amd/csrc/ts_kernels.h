@@ -56,20 +56,24 @@ BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity);
 hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_t* rect,
                         int64_t N, const uint32_t* d_n, const ts_view* views, int64_t per_view,
                         int tiles_x, int num_tiles, const BinWorkspace& ws, const ts_bins& out,
-                        uint32_t* h_count, bool* overflow, hipStream_t stream);
+                        uint32_t* h_count, bool* overflow, hipStream_t stream,
+                        const uint32_t* d_tiles = nullptr);
 
+// `order` (nullable) lists the tiles in the order the workgroups take them.
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
-                           const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
-                           float* rgb, float* alpha, float* depth, float* T_final,
+                           const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
+                           int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
                            uint32_t* last, hipStream_t stream);
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
-                                 const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
+                                 const uint32_t* order, const ts_view* views,
+                                 const uint32_t* ctl, const Cfg& cfg,
                                  uint32_t* queue, int workgroups, float* rgb, float* alpha,
                                  float* depth, hipStream_t stream);
 
 void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
-                            const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
+                            const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
+                            int num_tiles,
                             const float* dL_drgb, const float* dL_dalpha,
                             const float* dL_ddepth, const float* T_final,
                             const uint32_t* last, float* g2d, hipStream_t stream);

@@ -46,6 +46,7 @@ class ViewState:
         self.ntiles = torch.empty(n, dtype=torch.int32, device=dev)
         self.g2d = torch.empty((n, B.TS_G2D_STRIDE), dtype=torch.float32, device=dev)
         self.ranges = torch.empty((self.num_tiles, 2), dtype=torch.int32, device=dev)
+        self.order = torch.empty(max(self.num_tiles, 1), dtype=torch.int32, device=dev)
         self.d_count = torch.zeros(4, dtype=torch.int32, device=dev)
         self.want_keys = keys
         self._alloc_lists(capacity)
@@ -64,7 +65,7 @@ class ViewState:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.bins = B.ts_bins(None if self.keys is None else self.keys.data_ptr(),
                               self.vals.data_ptr(), self.ranges.data_ptr(),
-                              self.d_count.data_ptr(), self.capacity)
+                              self.d_count.data_ptr(), self.capacity, self.order.data_ptr())
 
     def outputs(self) -> Outputs:
         dev, H, W = self.device, self.H, self.W

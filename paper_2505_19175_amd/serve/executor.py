@@ -51,6 +51,7 @@ class BatchedExecutor:
             s.ntiles = torch.empty(n, dtype=torch.int32, device=dev)
             s.vals = torch.empty(capacity, dtype=torch.int32, device=dev)
             s.ranges = torch.empty((max_tiles, 2), dtype=torch.int32, device=dev)
+            s.order = torch.empty(max_tiles, dtype=torch.int32, device=dev)
             s.d_count = torch.zeros(4, dtype=torch.int32, device=dev)
             s.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
             s.rgb = torch.empty(3 * max_pixels, dtype=torch.float32, device=dev)
@@ -63,7 +64,7 @@ class BatchedExecutor:
             s.proj = B.ts_proj(s.rec.data_ptr(), s.rect.data_ptr(), s.depth_key.data_ptr(),
                                s.ntiles.data_ptr(), None)
             s.bins = B.ts_bins(None, s.vals.data_ptr(), s.ranges.data_ptr(), s.d_count.data_ptr(),
-                               capacity)
+                               capacity, s.order.data_ptr())
             s.stream = torch.cuda.Stream(device=dev)
             s.event = torch.cuda.Event()
             s.batch = None

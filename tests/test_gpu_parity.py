@@ -63,6 +63,11 @@ def _check_bins(st, scene, cam, cfg):
     np.testing.assert_array_equal(ranges, ref["ranges"])
     dc = st.d_count.cpu().numpy()
     assert dc[0] == M and dc[1] == int((ref["setup"]["ntiles"] > 0).sum()) and dc[2] == 0
+    # raster order: a permutation of the tiles by non-increasing list length
+    order = st.order.cpu().numpy()[: ref["n_tiles"]].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(ref["n_tiles"]))
+    lens = np.minimum((ref["ranges"][:, 1] - ref["ranges"][:, 0]).astype(np.int64), 2047)[order]
+    assert np.all(np.diff(lens) <= 0)
     return M
 
 
