@@ -122,9 +122,10 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
     bool overflow = false;
     hipError_t e;
     if (N == 0) {
-        // empty scene: zero counts and ranges
+        // empty scene: zero counts and ranges, and a valid tile order
         ts::launch_fill_u32(out->d_count, 4, 0u, stream);
         ts::launch_fill_u32(out->ranges, 2 * (int64_t)num_tiles, 0u, stream);
+        ts::launch_tile_order(out->ranges, num_tiles, nullptr, out->order, stream);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "ts_bin_sort");
         if (h_count) {

@@ -450,6 +450,14 @@ __global__ __launch_bounds__(256) void k_tile_order(const uint32_t* __restrict__
     for (int t = threadIdx.x; t < n; t += kBlock) order[atomicAdd(&h[key(t)], 1u)] = (uint32_t)t;
 }
 
+void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
+                       uint32_t* order, hipStream_t stream)
+{
+    if (order && num_tiles > 0)
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kBlock), 0, stream, ranges, num_tiles,
+                           d_tiles, order);
+}
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tfin,
                                                 const uint32_t* __restrict__ vals,
                                                 const float* __restrict__ depth,
@@ -554,9 +562,7 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     if (m_max > 0)
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((m_max + 255) / 256)), dim3(256), 0, stream,
                            ws.tfin, out.vals, depth, d_sortn, out.ranges, out.keys);
-    if (out.order)
-        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kBlock), 0, stream, out.ranges, num_tiles,
-                           d_tiles, out.order);
+    launch_tile_order(out.ranges, num_tiles, d_tiles, out.order, stream);
     return hipGetLastError();
 }
 

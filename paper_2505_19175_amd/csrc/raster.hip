@@ -1,17 +1,24 @@
 // raster.hip -- per-tile compositing on gfx950: forward (front to back) and
 // backward (back to front, transmittance recovered from the final value).
 //
-// One 256-thread workgroup per 16x16 tile; wave w owns the 8x8 quadrant
-// (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) of it.  The tile's list
-// is walked in batches of 256 entries staged through LDS: each thread copies
-// one record as seven 16-byte chunks into chunk-major arrays (consecutive
-// lanes write consecutive 16-byte slots, so the staging writes are free of
-// bank conflicts) and marks the quadrants the record's tight box touches.
-// Each wave then visits only the entries that touch its quadrant, found by
-// scalar bit scans of ballot masks, and reads each one as LDS broadcasts.
+// One 256-thread workgroup per 16x16 tile.  Wave w owns the 8x8 quadrant
+// (w & 1, w >> 1) and each of its four 16-lane rows (a DPP row) owns a 4x4
+// block of it: lane l shades pixel (l & 3, (l >> 2) & 3) of block
+// g = l >> 4 = (g & 1, g >> 1).
+//
+// The tile's list is walked in batches of 256 entries staged through LDS:
+// each thread copies one record as seven 16-byte chunks into chunk-major
+// arrays (consecutive lanes write consecutive slots: no bank conflicts) and
+// marks the 4x4 blocks of the tile its tight box touches.  Every row of a
+// wave then walks its own list of entries -- the ones touching its block --
+// so one wave step advances four lists at once.  Triangles here cover a few
+// pixels, so per-block lists are ~2.4x shorter per step than one list for
+// the whole 8x8 quadrant.  List heads are popped with scalar bit scans of
+// ballot masks; each lane reads its row's record from LDS.
+//
 // The window is evaluated as three FP64 affine functions per pixel (gfx950
 // issues v_fma_f64 at the rate of unpacked v_fma_f32); the rest is FP32,
-// written without branches so a wave issues one path per entry.
+// written without branches so a wave issues one path per step.
 #include "ts_device.h"
 #include "ts_kernels.h"
 
@@ -19,10 +26,11 @@ namespace ts {
 
 constexpr int kBatch = kBlock;   // entries staged per batch
 constexpr int kChunks = 7;       // 16-byte chunks of a record the raster reads
+constexpr int kMasks = kBatch / 64;
 
 struct Stage {
     float4 q[kChunks][kBatch];
-    uint8_t hit[kBatch];
+    uint16_t hit[kBatch];        // bit 4 w + g: touches block g of quadrant w
 };
 
 union RecView {
@@ -30,13 +38,8 @@ union RecView {
     TriRecord r;
 };
 
-__device__ __forceinline__ bool quad_hit(const TriRecord& r, int qx0, int qy0)
-{
-    return r.px0 <= qx0 + 7 && r.px1 >= qx0 && r.py0 <= qy0 + 7 && r.py1 >= qy0;
-}
-
-// Copy record `tri` into LDS slot threadIdx.x; return the 4-bit mask of the
-// tile's 8x8 quadrants its tight box touches (bit w = quadrant of wave w).
+// Copy record `tri` into LDS slot threadIdx.x and return the mask of the
+// tile's sixteen 4x4 blocks its tight box touches.
 __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restrict__ rec,
                                               uint32_t tri, int tx0, int ty0)
 {
@@ -46,10 +49,21 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
     for (int c = 0; c < kChunks; ++c) u.q[c] = src[c];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = u.q[c];
+    uint32_t cx = 0, cy = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int x0 = tx0 + 4 * i, y0 = ty0 + 4 * i;
+        cx |= (u.r.px0 <= x0 + 3 && u.r.px1 >= x0) ? (1u << i) : 0u;
+        cy |= (u.r.py0 <= y0 + 3 && u.r.py1 >= y0) ? (1u << i) : 0u;
+    }
     uint32_t m = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
-        m |= quad_hit(u.r, tx0 + (w & 1) * 8, ty0 + (w >> 1) * 8) ? (1u << w) : 0u;
+    for (int by = 0; by < 4; ++by)
+#pragma unroll
+        for (int bx = 0; bx < 4; ++bx) {
+            const int w = (bx >> 1) + 2 * (by >> 1), g = (bx & 1) + 2 * (by & 1);
+            m |= (((cx >> bx) & (cy >> by)) & 1u) << (4 * w + g);
+        }
     return m;
 }
 
@@ -62,16 +76,67 @@ __device__ __forceinline__ TriRecord read_rec(const Stage& S, int j)
     return u.r;
 }
 
-// Entries of the current batch whose box touches wave w's quadrant: one
-// 64-bit mask per 64 entries.
-__device__ __forceinline__ void wave_hits(const uint8_t* s_hit, int n, int w, int lane,
-                                          uint64_t (&hits)[kBatch / 64])
+// One row's entry list of the current batch: bit b of word c set when entry
+// 64 c + b touches the row's block.  Wave-uniform, kept in scalar registers.
+struct List {
+    uint64_t m0, m1, m2, m3;
+};
+static_assert(kMasks == 4, "List holds four 64-entry words");
+
+// Lists of the four rows of wave w.
+__device__ __forceinline__ void row_lists(const uint16_t* s_hit, int n, int w, int lane,
+                                          List& L0, List& L1, List& L2, List& L3)
 {
+    uint32_t h[4];
 #pragma unroll
-    for (int c = 0; c < kBatch / 64; ++c) {
+    for (int c = 0; c < 4; ++c) {
         const int j = c * 64 + lane;
-        hits[c] = __ballot(j < n && ((s_hit[j] >> w) & 1u));
+        h[c] = j < n ? (uint32_t)s_hit[j] >> (4 * w) : 0u;
     }
+    L0 = {__ballot(h[0] & 1u), __ballot(h[1] & 1u), __ballot(h[2] & 1u), __ballot(h[3] & 1u)};
+    L1 = {__ballot(h[0] & 2u), __ballot(h[1] & 2u), __ballot(h[2] & 2u), __ballot(h[3] & 2u)};
+    L2 = {__ballot(h[0] & 4u), __ballot(h[1] & 4u), __ballot(h[2] & 4u), __ballot(h[3] & 4u)};
+    L3 = {__ballot(h[0] & 8u), __ballot(h[1] & 8u), __ballot(h[2] & 8u), __ballot(h[3] & 8u)};
+}
+
+// Remove and return the first (last) entry of a list; -1 when it is empty.
+__device__ __forceinline__ int pop_front(List& L)
+{
+    int b;
+    if (L.m0) { b = __builtin_ctzll(L.m0); L.m0 &= L.m0 - 1ull; return b; }
+    if (L.m1) { b = __builtin_ctzll(L.m1); L.m1 &= L.m1 - 1ull; return 64 + b; }
+    if (L.m2) { b = __builtin_ctzll(L.m2); L.m2 &= L.m2 - 1ull; return 128 + b; }
+    if (L.m3) { b = __builtin_ctzll(L.m3); L.m3 &= L.m3 - 1ull; return 192 + b; }
+    return -1;
+}
+
+__device__ __forceinline__ int pop_back(List& L)
+{
+    int b;
+    if (L.m3) { b = 63 - __builtin_clzll(L.m3); L.m3 &= ~(1ull << b); return 192 + b; }
+    if (L.m2) { b = 63 - __builtin_clzll(L.m2); L.m2 &= ~(1ull << b); return 128 + b; }
+    if (L.m1) { b = 63 - __builtin_clzll(L.m1); L.m1 &= ~(1ull << b); return 64 + b; }
+    if (L.m0) { b = 63 - __builtin_clzll(L.m0); L.m0 &= ~(1ull << b); return b; }
+    return -1;
+}
+
+__device__ __forceinline__ uint64_t below(int lim)   // bits [0, lim) of a word, lim clamped
+{
+    return lim <= 0 ? 0ull : lim >= 64 ? ~0ull : ((1ull << lim) - 1ull);
+}
+
+// Keep only entries j < lim of a list.
+__device__ __forceinline__ void trim(List& L, int lim)
+{
+    L.m0 &= below(lim);
+    L.m1 &= below(lim - 64);
+    L.m2 &= below(lim - 128);
+    L.m3 &= below(lim - 192);
+}
+
+__device__ __forceinline__ int per_row(int g, int j0, int j1, int j2, int j3)
+{
+    return g == 0 ? j0 : g == 1 ? j1 : g == 2 ? j2 : j3;
 }
 
 // Window and opacity of a record at pixel offset (dx, dy); u <= 0 gives
@@ -84,6 +149,23 @@ __device__ __forceinline__ double frag_alpha(const TriRecord& r, int dx, int dy,
     window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
     f.k = k;
     return u;
+}
+
+struct Pix {
+    int w, g, i;    // wave, row, lane within the row
+    int px, py;
+};
+
+__device__ __forceinline__ Pix pixel_of(int tx, int ty)
+{
+    Pix P;
+    const int tid = threadIdx.x, lane = tid & 63;
+    P.w = tid >> 6;
+    P.g = lane >> 4;
+    P.i = lane & 15;
+    P.px = tx * kTile + (P.w & 1) * 8 + (P.g & 1) * 4 + (P.i & 3);
+    P.py = ty * kTile + (P.w >> 1) * 8 + (P.g >> 1) * 4 + (P.i >> 2);
+    return P;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,10 +187,9 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
                                          const uint32_t* __restrict__ vals, const Cfg& cfg,
                                          const TileJob& J, Stage& S)
 {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int qx0 = J.tx * kTile + (w & 1) * 8, qy0 = J.ty * kTile + (w >> 1) * 8;
-    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
-    const bool inside = px < J.W && py < J.H;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const Pix P = pixel_of(J.tx, J.ty);
+    const bool inside = P.px < J.W && P.py < J.H;
     const uint32_t start = J.start, end = J.end;
 
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
@@ -118,41 +199,43 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     for (uint32_t b = start; b < end; b += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b);
         __syncthreads();
-        if (tid < n) S.hit[tid] = (uint8_t)stage_rec(S, rec, vals[b + tid], J.tx * kTile, J.ty * kTile);
+        if (tid < n)
+            S.hit[tid] = (uint16_t)stage_rec(S, rec, vals[b + tid], J.tx * kTile, J.ty * kTile);
         __syncthreads();
-        uint64_t hits[kBatch / 64];
-        wave_hits(S.hit, n, w, lane, hits);
-        bool wave_done = __ballot(!done) == 0ull;
-        for (int c = 0; c < kBatch / 64 && !wave_done; ++c) {
-            uint64_t m = hits[c];
-            while (m != 0ull) {
-                const int j = c * 64 + __builtin_ctzll(m);
-                m &= m - 1ull;
-                const TriRecord r = read_rec(S, j);
-                Frag f;
-                const double u = frag_alpha(r, px - r.ax, py - r.ay, cfg.alpha_max, f);
-                const bool contrib = !done && u > 0.0 && f.a >= cfg.alpha_min;
-                const float Tn = T * (1.f - f.a);
-                const bool stop = contrib && Tn < cfg.T_min;
-                const bool comp = contrib && !stop;
-                const float wgt = comp ? f.a * T : 0.f;
-                C0 = fmaf(wgt, r.rgb[0], C0);
-                C1 = fmaf(wgt, r.rgb[1], C1);
-                C2 = fmaf(wgt, r.rgb[2], C2);
-                D = fmaf(wgt, r.z, D);
-                T = comp ? Tn : T;
-                last = comp ? b - start + (uint32_t)j + 1u : last;
-                done = done || stop;
-                if (__ballot(!done) == 0ull) {
-                    wave_done = true;
-                    break;
-                }
-            }
+        List L0, L1, L2, L3;
+        row_lists(S.hit, n, P.w, lane, L0, L1, L2, L3);
+        uint64_t live = __ballot(!done);
+        while (live != 0ull) {
+            // rows whose pixels are all done stop walking their lists
+            if ((live & 0xffffull) == 0ull) trim(L0, 0);
+            if (((live >> 16) & 0xffffull) == 0ull) trim(L1, 0);
+            if (((live >> 32) & 0xffffull) == 0ull) trim(L2, 0);
+            if ((live >> 48) == 0ull) trim(L3, 0);
+            const int j0 = pop_front(L0), j1 = pop_front(L1);
+            const int j2 = pop_front(L2), j3 = pop_front(L3);
+            if ((j0 & j1 & j2 & j3) < 0) break;          // every list is empty
+            const int j = per_row(P.g, j0, j1, j2, j3);
+            const TriRecord r = read_rec(S, j < 0 ? 0 : j);
+            Frag f;
+            const double u = frag_alpha(r, P.px - r.ax, P.py - r.ay, cfg.alpha_max, f);
+            const bool contrib = j >= 0 && !done && u > 0.0 && f.a >= cfg.alpha_min;
+            const float Tn = T * (1.f - f.a);
+            const bool stop = contrib && Tn < cfg.T_min;
+            const bool comp = contrib && !stop;
+            const float wgt = comp ? f.a * T : 0.f;
+            C0 = fmaf(wgt, r.rgb[0], C0);
+            C1 = fmaf(wgt, r.rgb[1], C1);
+            C2 = fmaf(wgt, r.rgb[2], C2);
+            D = fmaf(wgt, r.z, D);
+            T = comp ? Tn : T;
+            last = comp ? b - start + (uint32_t)j + 1u : last;
+            done = done || stop;
+            live = __ballot(!done);
         }
         if (__syncthreads_and(done)) break;
     }
     if (inside) {
-        const int64_t p = (int64_t)py * J.W + px;
+        const int64_t p = (int64_t)P.py * J.W + P.px;
         const int64_t hw = (int64_t)J.W * J.H;
         J.rgb[p] = fmaf(cfg.bg[0], T, C0);
         J.rgb[hw + p] = fmaf(cfg.bg[1], T, C1);
@@ -167,11 +250,12 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
 __global__ __launch_bounds__(256) void k_raster_fwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
-    int tiles_x, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
+    int tiles_x, int num_tiles, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
     float* __restrict__ out_depth, float* __restrict__ out_T, uint32_t* __restrict__ out_last)
 {
     __shared__ Stage S;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
     TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
               ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last};
     fwd_tile(rec, vals, cfg, J, S);
@@ -198,6 +282,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
         const uint32_t q = s_t;
         if (q >= total) break;
         const uint32_t t = order ? order[q] : q;
+        if (t >= total) continue;
         uint32_t v = 0;
         while (v + 1 < nviews && views[v + 1].tile_offset <= t) ++v;
         const ts_view& V = views[v];
@@ -221,67 +306,75 @@ __device__ __forceinline__ float dpp(float x)
         float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
 }
 
-// Sum 16 per-lane values over the 64 lanes of a wave by transpose-and-add:
-// each step pairs lanes across one lane-index bit, and each lane keeps the
-// half of its values the partner sends it, so the values per lane halve.
-// Bits 5 and 4 use gfx950's v_permlane32_swap / v_permlane16_swap, bits 3
-// and 2 DPP row_ror:8 / row_half_mirror, then quad DPP adds finish.  No LDS
-// traffic.  On return lane L holds the total of slot L >> 2.
-__device__ __forceinline__ float wave_reduce16(const float (&v)[16], int lane)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t x)
 {
-    float a8[8], a4[4], a2[2];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
-                                                        __float_as_uint(v[i + 8]), false, false);
-        a8[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a8[i]),
-                                                        __float_as_uint(a8[i + 4]), false, false);
-        a4[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
-    }
-    const bool b3 = lane & 8;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float send = b3 ? a4[i] : a4[i + 2];
-        const float keep = b3 ? a4[i + 2] : a4[i];
-        a2[i] = keep + dpp<0x128>(send);          // row_ror:8 (partner lane ^ 8)
-    }
-    const bool b2 = lane & 4;
-    float x = (b2 ? a2[1] : a2[0]) + dpp<0x141>(b2 ? a2[0] : a2[1]);   // row_half_mirror
-    x += dpp<0x4E>(x);                             // quad_perm [2,3,0,1]
-    x += dpp<0xB1>(x);                             // quad_perm [1,0,3,2]
-    return x;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
 }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+// Sum 16 per-lane values over the 16 lanes of each DPP row by
+// transpose-and-add: each step pairs lanes across one bit of the lane index
+// within the row (row_ror:8, row_half_mirror, quad_perm) and each lane keeps
+// the half of its values its partner sends it, so the values per lane halve.
+// 45 VALU, no LDS.  On return lane i of a row holds the row total of slot i.
+__device__ __forceinline__ float row_reduce16(const float (&v)[16], int i)
 {
+    float a8[8], a4[4], a2[2];
+    const bool b3 = i & 8;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, d, 64));
+    for (int k = 0; k < 8; ++k) {
+        const float send = b3 ? v[k] : v[k + 8];
+        const float keep = b3 ? v[k + 8] : v[k];
+        a8[k] = keep + dpp<0x128>(send);           // row_ror:8      (partner i ^ 8)
+    }
+    const bool b2 = i & 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float send = b2 ? a8[k] : a8[k + 4];
+        const float keep = b2 ? a8[k + 4] : a8[k];
+        a4[k] = keep + dpp<0x141>(send);           // row_half_mirror (partner i ^ 7)
+    }
+    const bool b1 = i & 2;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float send = b1 ? a4[k] : a4[k + 2];
+        const float keep = b1 ? a4[k + 2] : a4[k];
+        a2[k] = keep + dpp<0x4E>(send);            // quad_perm [2,3,0,1] (partner i ^ 2)
+    }
+    const bool b0 = i & 1;
+    return (b0 ? a2[1] : a2[0]) + dpp<0xB1>(b0 ? a2[0] : a2[1]);   // quad_perm [1,0,3,2]
+}
+
+// Maximum over the 16 lanes of each row.
+__device__ __forceinline__ uint32_t row_max(uint32_t x)
+{
+    x = max(x, dpp_u<0x128>(x));
+    x = max(x, dpp_u<0x141>(x));
+    x = max(x, dpp_u<0x4E>(x));
+    x = max(x, dpp_u<0xB1>(x));
     return x;
 }
 
 __global__ __launch_bounds__(256) void k_raster_bwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
-    int tiles_x, const float* __restrict__ dL_drgb, const float* __restrict__ dL_dalpha,
-    const float* __restrict__ dL_ddepth, const float* __restrict__ T_final,
-    const uint32_t* __restrict__ last_in, float* __restrict__ g2d)
+    int tiles_x, int num_tiles, const float* __restrict__ dL_drgb,
+    const float* __restrict__ dL_dalpha, const float* __restrict__ dL_ddepth,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ last_in,
+    float* __restrict__ g2d)
 {
     __shared__ Stage S;
     __shared__ uint32_t s_tri[kBatch];
     __shared__ uint32_t s_max;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
     const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int qx0 = tx * kTile + (w & 1) * 8, qy0 = ty * kTile + (w >> 1) * 8;
-    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
-    const bool inside = px < cam.W && py < cam.H;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const Pix P = pixel_of(tx, ty);
+    const bool inside = P.px < cam.W && P.py < cam.H;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
 
-    const int64_t p = (int64_t)py * cam.W + px;
+    const int64_t p = (int64_t)P.py * cam.W + P.px;
     const int64_t hw = (int64_t)cam.W * cam.H;
     float T = 1.f, Tf = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gA = 0.f, gD = 0.f;
     uint32_t my_last = 0;
@@ -299,11 +392,16 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
     // the background seen through the remaining transmittance
     const float gT = gA - (g0 * cfg.bg[0] + g1 * cfg.bg[1] + g2 * cfg.bg[2]);
     float S0 = 0.f, S1 = 0.f, S2 = 0.f, SD = 0.f;   // sum of w c and w z behind
-    const uint32_t wave_last = wave_max(my_last);   // entries this wave needs
 
+    // entries each row needs: up to the last one any of its pixels composited
+    const uint32_t rmax = row_max(my_last);
+    const int rl0 = (int)__builtin_amdgcn_readlane(rmax, 0);
+    const int rl1 = (int)__builtin_amdgcn_readlane(rmax, 16);
+    const int rl2 = (int)__builtin_amdgcn_readlane(rmax, 32);
+    const int rl3 = (int)__builtin_amdgcn_readlane(rmax, 48);
     if (tid == 0) s_max = 0u;
     __syncthreads();
-    if (lane == 0) atomicMax(&s_max, wave_last);
+    if (lane == 0) atomicMax(&s_max, (uint32_t)max(max(rl0, rl1), max(rl2, rl3)));
     __syncthreads();
     const uint32_t jmax = s_max;   // entries any pixel of the tile needs
 
@@ -314,68 +412,64 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         if (tid < n) {
             const uint32_t tri = vals[start + lo_ + tid];
             s_tri[tid] = tri;
-            S.hit[tid] = (uint8_t)stage_rec(S, rec, tri, tx * kTile, ty * kTile);
+            S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, tx * kTile, ty * kTile);
         }
         __syncthreads();
-        uint64_t hits[kBatch / 64];
-        wave_hits(S.hit, n, w, lane, hits);
-        // drop entries past the last one any pixel of this wave composited
-        const int lim = wave_last > lo_ ? (int)min(wave_last - lo_, (uint32_t)n) : 0;
-#pragma unroll
-        for (int c = 0; c < kBatch / 64; ++c) {
-            const int keep = min(max(lim - c * 64, 0), 64);
-            hits[c] &= keep == 64 ? ~0ull : ((1ull << keep) - 1ull);
-        }
-        for (int c = kBatch / 64 - 1; c >= 0; --c) {
-            uint64_t m = hits[c];
-            while (m != 0ull) {
-                const int jj = 63 - __builtin_clzll(m);   // back to front
-                m &= ~(1ull << jj);
-                const int j = c * 64 + jj;
-                const uint32_t idx = lo_ + (uint32_t)j;   // entry index within the tile
-                const TriRecord r = read_rec(S, j);
-                const int dx = px - r.ax, dy = py - r.ay;
-                Frag f;
-                const double u = frag_alpha(r, dx, dy, cfg.alpha_max, f);
-                const bool contrib = inside && idx < my_last && u > 0.0 && f.a >= cfg.alpha_min;
-                if (__ballot(contrib) == 0ull) continue;
+        List L0, L1, L2, L3;
+        row_lists(S.hit, n, P.w, lane, L0, L1, L2, L3);
+        trim(L0, rl0 - (int)lo_);
+        trim(L1, rl1 - (int)lo_);
+        trim(L2, rl2 - (int)lo_);
+        trim(L3, rl3 - (int)lo_);
+        for (;;) {
+            const int j0 = pop_back(L0), j1 = pop_back(L1);
+            const int j2 = pop_back(L2), j3 = pop_back(L3);
+            if ((j0 & j1 & j2 & j3) < 0) break;          // every list is empty
+            const int j = per_row(P.g, j0, j1, j2, j3);
+            const int jc = j < 0 ? 0 : j;
+            const TriRecord r = read_rec(S, jc);
+            const int dx = P.px - r.ax, dy = P.py - r.ay;
+            Frag f;
+            const double u = frag_alpha(r, dx, dy, cfg.alpha_max, f);
+            const bool contrib = j >= 0 && inside && lo_ + (uint32_t)j < my_last && u > 0.0 &&
+                                 f.a >= cfg.alpha_min;
+            if (__ballot(contrib) == 0ull) continue;
 
-                const float rom = __builtin_amdgcn_rcpf(1.f - f.a);
-                const float Ti = T * rom;           // transmittance before this fragment
-                const float wgt = contrib ? f.a * Ti : 0.f;
-                float v[16];
-                v[11] = g0 * wgt;
-                v[12] = g1 * wgt;
-                v[13] = g2 * wgt;
-                v[14] = gD * wgt;
-                v[15] = 0.f;
-                const float ga = g0 * (r.rgb[0] * Ti - S0 * rom) + g1 * (r.rgb[1] * Ti - S1 * rom) +
-                                 g2 * (r.rgb[2] * Ti - S2 * rom) + gD * (r.z * Ti - SD * rom) +
-                                 gT * Tf * rom;
-                S0 = fmaf(wgt, r.rgb[0], S0);
-                S1 = fmaf(wgt, r.rgb[1], S1);
-                S2 = fmaf(wgt, r.rgb[2], S2);
-                SD = fmaf(wgt, r.z, SD);
-                T = contrib ? Ti : T;
-                const bool open = contrib && f.oI <= cfg.alpha_max;   // not clamped
-                const float gI = ga * r.o;
-                v[9] = open ? ga * f.I : 0.f;                                  // dL/do
-                v[10] = open ? gI * f.I * (f.lg * 0.69314718055994531f) : 0.f;  // I ln u
-                const float gu = open ? gI * r.sigma * f.I * __builtin_amdgcn_rcpf(f.u) : 0.f;
-                const float a_ = gu * (float)dx, b_ = gu * (float)dy;
-                v[0] = f.k == 0 ? a_ : 0.f;
-                v[1] = f.k == 1 ? a_ : 0.f;
-                v[2] = f.k == 2 ? a_ : 0.f;
-                v[3] = f.k == 0 ? b_ : 0.f;
-                v[4] = f.k == 1 ? b_ : 0.f;
-                v[5] = f.k == 2 ? b_ : 0.f;
-                v[6] = f.k == 0 ? gu : 0.f;
-                v[7] = f.k == 1 ? gu : 0.f;
-                v[8] = f.k == 2 ? gu : 0.f;
-                const float tot = wave_reduce16(v, lane);
-                if ((lane & 3) == 0 && (lane >> 2) < 15 && tot != 0.f)
-                    unsafeAtomicAdd(g2d + (int64_t)s_tri[j] * TS_G2D_STRIDE + (lane >> 2), tot);
-            }
+            const float rom = __builtin_amdgcn_rcpf(1.f - f.a);
+            const float Ti = T * rom;           // transmittance before this fragment
+            const float wgt = contrib ? f.a * Ti : 0.f;
+            float v[16];
+            v[11] = g0 * wgt;
+            v[12] = g1 * wgt;
+            v[13] = g2 * wgt;
+            v[14] = gD * wgt;
+            v[15] = 0.f;
+            const float ga = g0 * (r.rgb[0] * Ti - S0 * rom) + g1 * (r.rgb[1] * Ti - S1 * rom) +
+                             g2 * (r.rgb[2] * Ti - S2 * rom) + gD * (r.z * Ti - SD * rom) +
+                             gT * Tf * rom;
+            S0 = fmaf(wgt, r.rgb[0], S0);
+            S1 = fmaf(wgt, r.rgb[1], S1);
+            S2 = fmaf(wgt, r.rgb[2], S2);
+            SD = fmaf(wgt, r.z, SD);
+            T = contrib ? Ti : T;
+            const bool open = contrib && f.oI <= cfg.alpha_max;   // not clamped
+            const float gI = ga * r.o;
+            v[9] = open ? ga * f.I : 0.f;                                  // dL/do
+            v[10] = open ? gI * f.I * (f.lg * 0.69314718055994531f) : 0.f;  // I ln u
+            const float gu = open ? gI * r.sigma * f.I * __builtin_amdgcn_rcpf(f.u) : 0.f;
+            const float a_ = gu * (float)dx, b_ = gu * (float)dy;
+            v[0] = f.k == 0 ? a_ : 0.f;
+            v[1] = f.k == 1 ? a_ : 0.f;
+            v[2] = f.k == 2 ? a_ : 0.f;
+            v[3] = f.k == 0 ? b_ : 0.f;
+            v[4] = f.k == 1 ? b_ : 0.f;
+            v[5] = f.k == 2 ? b_ : 0.f;
+            v[6] = f.k == 0 ? gu : 0.f;
+            v[7] = f.k == 1 ? gu : 0.f;
+            v[8] = f.k == 2 ? gu : 0.f;
+            const float tot = row_reduce16(v, P.i);
+            if (j >= 0 && P.i < 15 && tot != 0.f)
+                unsafeAtomicAdd(g2d + (int64_t)s_tri[jc] * TS_G2D_STRIDE + P.i, tot);
         }
         hi_ = lo_;
     }
@@ -388,7 +482,7 @@ void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t
 {
     hipLaunchKernelGGL(k_raster_fwd, dim3(num_tiles), dim3(kBlock), 0, stream,
                        reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, rgb, alpha, depth, T_final, last);
+                       tiles_x, num_tiles, rgb, alpha, depth, T_final, last);
 }
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
@@ -410,7 +504,7 @@ void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_
 {
     hipLaunchKernelGGL(k_raster_bwd, dim3(num_tiles), dim3(kBlock), 0, stream,
                        reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, g2d);
+                       tiles_x, num_tiles, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, g2d);
 }
 
 }  // namespace ts

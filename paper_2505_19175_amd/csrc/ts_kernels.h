@@ -32,6 +32,11 @@ void launch_backproject(const float* v, const float* sh, int64_t N, const Cam& c
 // p[0..n) = x (a kernel, so it can sit inside a captured graph).
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream);
 
+// order[0..n) = tiles by decreasing list length, n = min(*d_tiles,
+// num_tiles) or num_tiles; nothing when order is null.
+void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
+                       uint32_t* order, hipStream_t stream);
+
 // Workspace carve-up of the binning stage.
 struct BinWorkspace {
     uint32_t* blk;      // [nbN + 1] block sums / offsets

@@ -211,6 +211,9 @@ def test_empty_and_fully_culled():
     ras, st, sct, out = G.gpu_forward(empty, cam, cfg)
     o = G.to_np(out)
     assert st.M == 0 and np.all(o["alpha"] == 0) and np.all(o["T_final"] == 1)
+    # the empty path still writes a valid raster order (regression: it used to
+    # leave the order uninitialised and the raster read ranges out of bounds)
+    assert np.array_equal(np.sort(st.order.cpu().numpy()), np.arange(st.num_tiles))
     behind = box = synth.box_soup(5, 50)
     behind.v[:, :, 2] = -1.0                                  # all behind the camera
     ras, st, sct, out = G.gpu_forward(behind, cam, cfg)
