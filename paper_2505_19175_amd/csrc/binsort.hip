@@ -547,8 +547,11 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
         err = hipStreamSynchronize(stream);
         if (err != hipSuccess) return err;
         if ((uint64_t)h_count[0] > out.capacity) {
+            // ranges are all empty here; keep the order valid for any raster
+            // launched before the caller grows the list
             *overflow = true;
-            return hipSuccess;
+            launch_tile_order(out.ranges, num_tiles, d_tiles, out.order, stream);
+            return hipGetLastError();
         }
         m_max = h_count[0];
     }
