@@ -8,6 +8,7 @@ workload (SH degree 3, 70% dense clusters + 30% background shell,
 gradient resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--view 0|1] [--no-cpu-baseline]
+                  [--no-serve] [--no-other-view]
 """
 from __future__ import annotations
 
@@ -114,14 +115,16 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device to device (scale for HBM counters)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-other-view", action="store_true",
+                    help="skip the second 3M-triangle view (1600x1040 for pose 0)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,4000,8000",
                     help="req/s; the quoted 200-2000 plus two rates past saturation")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="load duration per rate, the first 0.5 s not measured")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the renderer runs on exactly one GPU: --gpus must be 1 "
+                                   "(sharding across GPUs is not implemented)"}))
         sys.exit(2)
 
     import numpy as np
@@ -147,67 +150,79 @@ def main():
     log(f"[bench] generated {wl.scene.n} triangles in {time.perf_counter() - t0:.1f}s")
     scene_t = scene_to_device(wl.scene, dev)
     W, H, N = cam.width, cam.height, wl.scene.n
-    dC_np, _, _ = synth.upstream(wl.upstream_seed, W, H)
-    dC = torch.tensor(dC_np, device=dev)
 
-    # size the instance list once with a host read-back, then run without one
-    ras = Rasterizer(cfg, device=dev)
-    st = ViewState(N, W, H, 4 * N, device=dev)
-    out = ras.forward(st, scene_t, cam, sync=True)
-    M, N_v = st.M, st.N_v
-    st._alloc_lists(int(M * 1.05) + 4096)
-    ccam = B.make_camera(cam)
     ccfg = B.make_config(cfg)
     v, o, sg, sh = scene_t
     gv, go, gs, gsh = (torch.empty_like(t) for t in scene_t)
     stream = torch.cuda.current_stream()
     sh_ = stream.cuda_stream
-    log(f"[bench] N={N} N_v={N_v} M={M} {W}x{H}")
+    ras = Rasterizer(cfg, device=dev)
+
+    def prepare(view_cam):
+        """Buffers of one view; the instance list is sized once with a host
+        read-back, then every step runs without one."""
+        Wv, Hv = view_cam.width, view_cam.height
+        stv = ViewState(N, Wv, Hv, 4 * N, device=dev)
+        outv = ras.forward(stv, scene_t, view_cam, sync=True)
+        stv._alloc_lists(int(stv.M * 1.05) + 4096)
+        up, _, _ = synth.upstream(wl.upstream_seed, Wv, Hv)
+        return stv, outv, B.make_camera(view_cam), torch.tensor(up, device=dev)
+
+    def make_step(stv, outv, ccam, dCv):
+        def step(ev=None):
+            if ev: ev[0].record(stream)
+            B.ts_project(v, o, sg, sh, N, ccam, ccfg, stv.proj, sh_)
+            if ev: ev[1].record(stream)
+            B.ts_bin_sort(stv.proj, N, ccam, stv.ws, stv.ws_bytes, stv.bins, None, sh_)
+            if ev: ev[2].record(stream)
+            B.ts_render_forward(stv.proj, stv.bins, ccam, ccfg, outv.rgb, outv.alpha, outv.depth,
+                                outv.T_final, outv.last, sh_)
+            if ev: ev[3].record(stream)
+            B.ts_raster_backward(stv.proj, stv.bins, ccam, ccfg, dCv, None, None, outv.T_final,
+                                 outv.last, sh_)
+            if ev: ev[4].record(stream)
+            B.ts_project_backward(v, sh, N, stv.proj, ccam, ccfg, gv, go, gs, gsh, sh_)
+            if ev: ev[5].record(stream)
+        return step
+
+    def timed(step, steps, warmup, stv):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        assert int(stv.d_count[2].item()) == 0, "instance list overflow"
+        # timed region: exactly `steps` steps, per-stage events on the launch stream
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        per = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(5)]
+                        for k in range(steps)])               # ms
+        gpu_total_ms = float(evs[0][0].elapsed_time(evs[-1][5]))
+        return max(gpu_total_ms, wall * 1e3) / steps, per
 
     stages = ["project", "bin_sort", "raster_fwd", "raster_bwd", "project_bwd"]
-
-    def step(ev=None):
-        if ev: ev[0].record(stream)
-        B.ts_project(v, o, sg, sh, N, ccam, ccfg, st.proj, sh_)
-        if ev: ev[1].record(stream)
-        B.ts_bin_sort(st.proj, N, ccam, st.ws, st.ws_bytes, st.bins, None, sh_)
-        if ev: ev[2].record(stream)
-        B.ts_render_forward(st.proj, st.bins, ccam, ccfg, out.rgb, out.alpha, out.depth,
-                            out.T_final, out.last, sh_)
-        if ev: ev[3].record(stream)
-        B.ts_raster_backward(st.proj, st.bins, ccam, ccfg, dC, None, None, out.T_final, out.last,
-                             sh_)
-        if ev: ev[4].record(stream)
-        B.ts_project_backward(v, sh, N, st.proj, ccam, ccfg, gv, go, gs, gsh, sh_)
-        if ev: ev[5].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    assert int(st.d_count[2].item()) == 0, "instance list overflow"
-
-    # timed region: exactly K steps, per-stage events on the launch stream
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    per = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(5)]
-                    for k in range(args.steps)])           # ms
-    step_ms = float(per.sum(1).mean())
-    gpu_total_ms = float(evs[0][0].elapsed_time(evs[-1][5]))
-    ms_per_step = max(gpu_total_ms, wall * 1e3) / args.steps
+    torch.cuda.reset_peak_memory_stats(dev)
+    st, out, ccam, dC = prepare(cam)
+    M, N_v = st.M, st.N_v
+    log(f"[bench] N={N} N_v={N_v} M={M} {W}x{H}")
+    ms_per_step, per = timed(make_step(st, out, ccam, dC), args.steps, args.warmup, st)
+    peak_bytes = int(torch.cuda.max_memory_allocated(dev))
     stage_ms = {s: round(float(per[:, j].mean()), 4) for j, s in enumerate(stages)}
 
     byt = algorithmic_bytes(N, N_v, M, W, H, K)
     single_kernel = ["project", "raster_fwd", "raster_bwd", "project_bwd"]
     dom = max(single_kernel, key=lambda s: stage_ms[s])
     ach = byt[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    tr = traffic_bytes(dom)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None}
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+            "traffic": None if tr is None else round(tr)}
     total_bytes = sum(byt.values())
+    step_gbs = total_bytes / (ms_per_step * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch, dev)
     res = {
         "metric": METRIC,
         "value": round(W * H / (ms_per_step * 1e-3) / 1e6, 3),
@@ -227,12 +242,37 @@ def main():
         "triangles_per_s": round(N / (ms_per_step * 1e-3), 1),
         "stage_ms": stage_ms,
         "stage_GBps_algorithmic": {s: round(byt[s] / (stage_ms[s] * 1e-3) / 1e9, 1) for s in stages},
-        "step_hbm_frac": round(total_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+        "step_hbm_frac": round(step_gbs / HBM_PEAK_GBS, 5),
+        "copy_GBps": round(copy_gbs, 1),
+        "step_copy_frac": round(step_gbs / copy_gbs, 5),
         "roofline": roof,
+        "memory": {"device_peak_bytes": peak_bytes,
+                   "backward_state_bytes": 8 * W * H,
+                   "note": "device peak over the timed steps of this view (scene, gradients, "
+                           "projection state, lists, images); the backward keeps 8 B per pixel "
+                           "(T_final, last) and no per-fragment state"},
     }
+    if not args.no_other_view:
+        ov = 1 - args.view if args.view in (0, 1) else 1
+        cam2 = wl.cameras[ov]
+        st2, out2, ccam2, dC2 = prepare(cam2)
+        ms2, per2 = timed(make_step(st2, out2, ccam2, dC2), 20, 3, st2)
+        res["other_view"] = {
+            "workload": f"tri3M_{cam2.width}x{cam2.height}, hemisphere pose {ov}",
+            "width": cam2.width, "height": cam2.height, "N_visible": st2.N_v,
+            "instances": st2.M, "steps": 20, "ms_per_step": round(ms2, 4),
+            "Mpixel_per_s": round(cam2.width * cam2.height / (ms2 * 1e-3) / 1e6, 3),
+            "stage_ms": {s: round(float(per2[:, j].mean()), 4) for j, s in enumerate(stages)}}
+        del st2, out2, dC2
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a pixel sample")
-        res["cpu_baseline"] = cpu_baseline(wl, cam, args.cpu_pixels)
+        res["cpu_baseline"], nfrag = cpu_baseline(wl, cam, args.cpu_pixels)
+        F_est = nfrag * W * H
+        res["memory"]["fragments_estimate"] = round(F_est)
+        res["memory"]["stored_fragment_bytes_estimate"] = round(12 * F_est)
+        res["memory"]["fragment_note"] = (
+            "F = composited fragments, the oracle's mean count on the sample pixels times W*H; "
+            "a backward that stored them would keep >= 12 B each (index, alpha, T)")
     if not args.no_serve:
         rates = [int(r) for r in args.serve_rates.split(",")]
         res["serve"] = serve_bench(rates, args.serve_seconds, 0.5)

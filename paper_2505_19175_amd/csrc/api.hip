@@ -85,9 +85,8 @@ int32_t ts_num_tiles(int32_t width, int32_t height)
 
 size_t ts_bin_sort_workspace_bytes(int64_t N, uint64_t capacity, int32_t num_tiles)
 {
-    (void)num_tiles;
-    if (N < 0) return 0;
-    return ts::carve_bin_workspace(nullptr, N, capacity).bytes;
+    if (N < 0 || num_tiles < 0) return 0;
+    return ts::carve_bin_workspace(nullptr, N, capacity, num_tiles).bytes;
 }
 
 int ts_project(const float* v, const float* o, const float* sigma, const float* sh, int64_t N,
@@ -116,9 +115,9 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
     if (!bins_ok(out)) return fail(TS_EINVAL, "ts_bin_sort: bad bins");
     if (N > 0 && !proj_ok(proj)) return fail(TS_EINVAL, "ts_bin_sort: bad projection");
     const int num_tiles = ts_num_tiles(cam->width, cam->height);
-    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, N, out->capacity);
+    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, N, out->capacity, num_tiles);
     if (!ws || ws_bytes < need.bytes) return fail(TS_EWORKSPACE, "ts_bin_sort: workspace too small");
-    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, N, out->capacity);
+    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, N, out->capacity, num_tiles);
     bool overflow = false;
     hipError_t e;
     if (N == 0) {
@@ -245,9 +244,8 @@ int ts_batch_layout(ts_view* views, int32_t n, uint32_t* total_tiles, uint64_t* 
 size_t ts_batch_workspace_bytes(int64_t N, int32_t max_views, uint64_t capacity,
                                 uint32_t max_tiles)
 {
-    (void)max_tiles;
     if (N < 0 || max_views <= 0) return 0;
-    return ts::carve_bin_workspace(nullptr, N * max_views, capacity).bytes + 256;
+    return ts::carve_bin_workspace(nullptr, N * max_views, capacity, max_tiles).bytes + 256;
 }
 
 int ts_render_forward_batched(const float* v, const float* o, const float* sigma,
@@ -266,10 +264,11 @@ int ts_render_forward_batched(const float* v, const float* o, const float* sigma
     if (!proj || !proj->rec || !proj->rect || !proj->depth || !proj->ntiles || !bins_ok(bins))
         return fail(TS_EINVAL, "ts_render_forward_batched: bad projection or bins");
     const int64_t entries = N * (int64_t)max_views;
-    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, entries, bins->capacity);
+    const ts::BinWorkspace need =
+        ts::carve_bin_workspace(nullptr, entries, bins->capacity, (int64_t)max_tiles);
     if (!ws || ws_bytes < need.bytes + 256)
         return fail(TS_EWORKSPACE, "ts_render_forward_batched: workspace too small");
-    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, entries, bins->capacity);
+    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, entries, bins->capacity, (int64_t)max_tiles);
     uint32_t* extra = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + need.bytes);
     uint32_t* queue = extra;        // tile queue head
     uint32_t* bctl = extra + 4;     // clamped descriptor: views, tiles, views * N

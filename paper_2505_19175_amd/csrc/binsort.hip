@@ -4,17 +4,21 @@
 // tile front to back by the depth key, ties by triangle index.  Sorting the
 // 64-bit (tile, depth) keys of all M instances would take 6 radix passes over
 // M.  Instead:
-//   1. compact the visible triangles in index order            (N_v entries)
-//   2. stable LSD radix sort of their depth keys, 4 x 8 bits   (N_v entries)
-//   3. scan their tile counts in that order and emit one instance per tile,
-//      so instances come out in (depth, index) order
-//   4. stable LSD radix sort of the instances by tile id,
-//      ceil(log2 tiles / 8) passes                               (M entries)
-// A stable sort by tile of a sequence already ordered by (depth, index) is
-// exactly the (tile, depth, index) order.
+//   1. count the tiles of every triangle, in index order, and scan the counts
+//   2. emit one instance per (triangle, tile) in index order
+//   3. stable LSD radix sort of the instances by tile id,
+//      ceil(log2 tiles / 8) passes over M; inside a tile the triangles are
+//      still in index order
+//   4. one workgroup per tile sorts that tile's entries by depth key with a
+//      stable block radix sort (in registers and LDS up to 2048 entries, in
+//      two global ping-pong buffers beyond), skipping the 8-bit digits that
+//      are equal over the whole tile
+// A stable sort by depth of a list in index order is the (depth, index)
+// order, so the result is exactly the (tile, depth, index) order.  Nothing is
+// gathered in a random order except the depth key of each instance.
 //
-// Every pass is reduce-then-scan: per-block digit histograms, a scan of the
-// histogram matrix, and a stable scatter whose in-block ranks come from
+// Every global pass is reduce-then-scan: per-block digit histograms, a scan
+// of the histogram matrix, and a stable scatter whose in-block ranks come from
 // wavefront ballots.  No kernel waits on another block, so nothing can spin.
 // Element counts are read from device memory, so the whole chain can run
 // without a host round trip (grids sized by upper bounds).
@@ -31,12 +35,12 @@ static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 __host__ __device__ static inline int64_t nblocks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
-BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity)
+BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity, int64_t num_tiles)
 {
     BinWorkspace w{};
     const int64_t nbN = nblocks(N > 0 ? N : 1);
     const int64_t nbC = nblocks(capacity > 0 ? (int64_t)capacity : 1);
-    w.hist_stride = nbN > nbC ? nbN : nbC;
+    w.hist_stride = nbC;
     char* p = reinterpret_cast<char*>(base);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -44,14 +48,9 @@ BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity)
         off += align256(bytes);
         return reinterpret_cast<uint32_t*>(q);
     };
-    const size_t n4 = 4 * (size_t)(N > 0 ? N : 1);
     const size_t c4 = 4 * (size_t)(capacity > 0 ? capacity : 1);
-    w.blk = take(4 * (size_t)(w.hist_stride + 1));
-    w.dk[0] = take(n4);
-    w.dk[1] = take(n4);
-    w.dv[0] = take(n4);
-    w.dv[1] = take(n4);
-    w.off = take(4);
+    w.blk = take(4 * (size_t)(nbN + 1));
+    w.blk_vis = take(4 * (size_t)(nbN + 1));
     w.hist = take(4 * (size_t)kRadix * (size_t)w.hist_stride);
     w.dtot = take(4 * kRadix);
     w.tk[0] = take(c4);
@@ -59,6 +58,7 @@ BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity)
     w.tv[0] = take(c4);
     w.tv[1] = take(c4);
     w.tfin = take(c4);
+    w.torder = take(4 * (size_t)(num_tiles > 0 ? num_tiles : 1));
     w.ctl = take(4 * 8);
     w.bytes = off;
     return w;
@@ -92,42 +92,51 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t& t
 }
 
 // ---------------------------------------------------------------------------
-// 1. compaction of visible triangles
+// 1. tile counts in index order
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restrict__ ntiles,
-                                                       int64_t N_host,
-                                                       const uint32_t* __restrict__ d_n,
-                                                       uint32_t* __restrict__ blk)
+// Per block of kChunk entries: the number of instances and of visible entries.
+__global__ __launch_bounds__(256) void k_count(const uint32_t* __restrict__ ntiles,
+                                               int64_t N_host, const uint32_t* __restrict__ d_n,
+                                               uint32_t* __restrict__ blk,
+                                               uint32_t* __restrict__ blk_vis)
 {
     __shared__ uint32_t s_tmp[4];
     const int64_t N = d_n ? (int64_t)*d_n : N_host;
     if ((int64_t)blockIdx.x >= nblocks(N)) return;
     const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
-    uint32_t c = 0;
+    uint32_t c = 0, v = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t i = base + r;
-        c += (i < N && ntiles[i] != 0u) ? 1u : 0u;
+        const uint32_t n = i < N ? ntiles[i] : 0u;
+        c += n;
+        v += n != 0u ? 1u : 0u;
     }
-    uint32_t tot;
+    uint32_t tot, tot_vis;
     block_exclusive_scan(c, tot, s_tmp);
-    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+    block_exclusive_scan(v, tot_vis, s_tmp);
+    if (threadIdx.x == 0) {
+        blk[blockIdx.x] = tot;
+        blk_vis[blockIdx.x] = tot_vis;
+    }
 }
 
 // Exclusive scan in place of the per-block sums (one workgroup).  The number
 // of blocks is nblocks(n) with n = *d_n (or n_host when d_n is null).  The
-// total goes to total_out[0]; if cap_out is set, min(total, cap) goes to
-// cap_out[0] and total > cap sets flag_out[0].
+// total goes to total_out[0]; min(total, cap) goes to cap_out[0] and
+// total > cap sets flag_out[0]; the plain sum of sum_blk goes to sum_out[0].
 __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
                                                      const uint32_t* __restrict__ d_n,
                                                      int64_t n_host, uint32_t* total_out,
                                                      uint32_t* cap_out, uint64_t cap,
-                                                     uint32_t* flag_out)
+                                                     uint32_t* flag_out,
+                                                     const uint32_t* __restrict__ sum_blk,
+                                                     uint32_t* sum_out)
 {
     __shared__ uint32_t s_tmp[4];
     const int64_t n = d_n ? (int64_t)*d_n : n_host;
     const int64_t nb = nblocks(n);
-    uint32_t running = 0;
+    uint32_t running = 0, other = 0;
     for (int64_t c0 = 0; c0 < nb; c0 += kBlock * 4) {
         uint32_t x[4], s = 0;
 #pragma unroll
@@ -135,6 +144,7 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
             const int64_t j = c0 + threadIdx.x * 4 + r;
             x[r] = j < nb ? blk[j] : 0u;
             s += x[r];
+            other += j < nb ? sum_blk[j] : 0u;
         }
         uint32_t tot;
         uint32_t pre = block_exclusive_scan(s, tot, s_tmp) + running;
@@ -146,48 +156,67 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
         }
         running += tot;
     }
+    uint32_t other_tot;
+    block_exclusive_scan(other, other_tot, s_tmp);
     if (threadIdx.x == 0) {
         total_out[0] = running;
-        if (cap_out) {
-            cap_out[0] = (uint64_t)running > cap ? (uint32_t)cap : running;
-            flag_out[0] = (uint64_t)running > cap ? 1u : 0u;
-        }
+        cap_out[0] = (uint64_t)running > cap ? (uint32_t)cap : running;
+        flag_out[0] = (uint64_t)running > cap ? 1u : 0u;
+        sum_out[0] = other_tot;
     }
 }
 
-__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ ntiles,
-                                                 const float* __restrict__ depth, int64_t N_host,
-                                                 const uint32_t* __restrict__ d_n,
-                                                 const uint32_t* __restrict__ blk,
-                                                 uint32_t* __restrict__ dk,
-                                                 uint32_t* __restrict__ dv)
+// ---------------------------------------------------------------------------
+// 2. instances in index order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntiles,
+                                              const short4* __restrict__ rect, int64_t N_host,
+                                              const uint32_t* __restrict__ d_n,
+                                              const uint32_t* __restrict__ blk, int tiles_x,
+                                              const ts_view* __restrict__ views, int64_t per_view,
+                                              uint64_t capacity, uint32_t* __restrict__ tk,
+                                              uint32_t* __restrict__ tv)
 {
     __shared__ uint32_t s_tmp[4];
     const int64_t N = d_n ? (int64_t)*d_n : N_host;
     if ((int64_t)blockIdx.x >= nblocks(N)) return;
     const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
-    uint32_t f[kItems], c = 0;
+    uint32_t cnt[kItems], c = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t i = base + r;
-        f[r] = (i < N && ntiles[i] != 0u) ? 1u : 0u;
-        c += f[r];
+        cnt[r] = i < N ? ntiles[i] : 0u;
+        c += cnt[r];
     }
     uint32_t tot;
-    uint32_t pos = block_exclusive_scan(c, tot, s_tmp) + blk[blockIdx.x];
+    uint64_t pos = block_exclusive_scan(c, tot, s_tmp) + (uint64_t)blk[blockIdx.x];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        if (f[r]) {
-            const int64_t i = base + r;
-            dk[pos] = __float_as_uint(depth[i]);   // positive floats order as unsigned ints
-            dv[pos] = (uint32_t)i;
-            ++pos;
+        if (cnt[r] == 0u) continue;
+        const uint32_t e = (uint32_t)(base + r);
+        const short4 rc = rect[e];
+        const int tx0 = rc.x / kTile, tx1 = rc.y / kTile;
+        const int ty0 = rc.z / kTile, ty1 = rc.w / kTile;
+        uint32_t toff = 0;
+        int tw = tiles_x;
+        if (views) {   // batched: entry = view * per_view + triangle
+            const ts_view& V = views[e / (uint64_t)per_view];
+            toff = V.tile_offset;
+            tw = (int)V.tiles_x;
         }
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) {
+                if (pos < capacity) {
+                    tk[pos] = toff + (uint32_t)(ty * tw + tx);
+                    tv[pos] = e;
+                }
+                ++pos;
+            }
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2./4. stable LSD radix sort pass (8-bit digit at `shift`)
+// 3. stable LSD radix sort pass (8-bit digit at `shift`)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ d_n, int shift,
@@ -307,77 +336,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------------------
-// 3. instances of the depth-sorted triangles
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_count_instances(const uint32_t* __restrict__ ntiles,
-                                                         const uint32_t* __restrict__ dv,
-                                                         const uint32_t* __restrict__ d_nv,
-                                                         uint32_t* __restrict__ blk)
-{
-    __shared__ uint32_t s_tmp[4];
-    const int64_t n = *d_nv;
-    if ((int64_t)blockIdx.x >= nblocks(n)) return;
-    const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
-    uint32_t c = 0;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t j = base + r;
-        c += j < n ? ntiles[dv[j]] : 0u;
-    }
-    uint32_t tot;
-    block_exclusive_scan(c, tot, s_tmp);
-    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntiles,
-                                              const short4* __restrict__ rect,
-                                              const uint32_t* __restrict__ dv,
-                                              const uint32_t* __restrict__ d_nv,
-                                              const uint32_t* __restrict__ blk, int tiles_x,
-                                              const ts_view* __restrict__ views, int64_t per_view,
-                                              uint64_t capacity, uint32_t* __restrict__ tk,
-                                              uint32_t* __restrict__ tv)
-{
-    __shared__ uint32_t s_tmp[4];
-    const int64_t n = *d_nv;
-    if ((int64_t)blockIdx.x >= nblocks(n)) return;
-    const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
-    uint32_t cnt[kItems], tri[kItems], c = 0;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t j = base + r;
-        tri[r] = j < n ? dv[j] : 0u;
-        cnt[r] = j < n ? ntiles[tri[r]] : 0u;
-        c += cnt[r];
-    }
-    uint32_t tot;
-    uint64_t pos = block_exclusive_scan(c, tot, s_tmp) + (uint64_t)blk[blockIdx.x];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        if (cnt[r] == 0u) continue;
-        const short4 rc = rect[tri[r]];
-        const int tx0 = rc.x / kTile, tx1 = rc.y / kTile;
-        const int ty0 = rc.z / kTile, ty1 = rc.w / kTile;
-        uint32_t toff = 0;
-        int tw = tiles_x;
-        if (views) {   // batched: entry = view * per_view + triangle
-            const ts_view& V = views[tri[r] / (uint64_t)per_view];
-            toff = V.tile_offset;
-            tw = (int)V.tiles_x;
-        }
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                if (pos < capacity) {
-                    tk[pos] = toff + (uint32_t)(ty * tw + tx);
-                    tv[pos] = tri[r];
-                }
-                ++pos;
-            }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// ranges and (optional) 64-bit keys
+// fills, batch descriptor, tile order, ranges
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t x)
 {
@@ -417,21 +376,33 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream)
 // launch.  One workgroup; ctl (optional) holds the number of tiles.
 constexpr int kLenBuckets = 2048;
 
+// n_long (optional) receives the number of tiles longer than kWaveMax: they
+// lead the order, since kWaveMax < kLenBuckets - 1.
+constexpr int kWaveMax = 1024;   // longest list one wave sorts on its own
+static_assert(kWaveMax < kLenBuckets - 1, "long tiles must lead the order");
+
 __global__ __launch_bounds__(256) void k_tile_order(const uint32_t* __restrict__ ranges,
                                                     int n_host, const uint32_t* __restrict__ d_n,
-                                                    uint32_t* __restrict__ order)
+                                                    uint32_t* __restrict__ order,
+                                                    uint32_t* __restrict__ n_long)
 {
     __shared__ uint32_t h[kLenBuckets];
     __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_long;
     const int n = d_n ? (int)min(*d_n, (uint32_t)n_host) : n_host;
     for (int b = threadIdx.x; b < kLenBuckets; b += kBlock) h[b] = 0u;
+    if (threadIdx.x == 0) s_long = 0u;
     __syncthreads();
+    auto len_of = [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; };
     auto key = [&](int t) {
-        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-        return (kLenBuckets - 1) - (int)min(len, (uint32_t)(kLenBuckets - 1));
+        return (kLenBuckets - 1) - (int)min(len_of(t), (uint32_t)(kLenBuckets - 1));
     };
-    for (int t = threadIdx.x; t < n; t += kBlock) atomicAdd(&h[key(t)], 1u);
+    for (int t = threadIdx.x; t < n; t += kBlock) {
+        atomicAdd(&h[key(t)], 1u);
+        if (len_of(t) > (uint32_t)kWaveMax) atomicAdd(&s_long, 1u);
+    }
     __syncthreads();
+    if (n_long && threadIdx.x == 0) n_long[0] = s_long;
     constexpr int per = kLenBuckets / kBlock;
     uint32_t loc[per], s = 0;
 #pragma unroll
@@ -451,19 +422,17 @@ __global__ __launch_bounds__(256) void k_tile_order(const uint32_t* __restrict__
 }
 
 void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
-                       uint32_t* order, hipStream_t stream)
+                       uint32_t* order, hipStream_t stream, uint32_t* n_long)
 {
     if (order && num_tiles > 0)
         hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kBlock), 0, stream, ranges, num_tiles,
-                           d_tiles, order);
+                           d_tiles, order, n_long);
 }
 
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tfin,
-                                                const uint32_t* __restrict__ vals,
-                                                const float* __restrict__ depth,
                                                 const uint32_t* __restrict__ d_m,
-                                                uint32_t* __restrict__ ranges,
-                                                uint64_t* __restrict__ keys)
+                                                uint32_t* __restrict__ ranges)
 {
     const int64_t m = *d_m;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -471,7 +440,418 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tfi
     const uint32_t t = tfin[p];
     if (p == 0 || tfin[p - 1] != t) ranges[2 * t] = (uint32_t)p;
     if (p == m - 1 || tfin[p + 1] != t) ranges[2 * t + 1] = (uint32_t)(p + 1);
-    if (keys) keys[p] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(depth[vals[p]]);
+}
+
+// ---------------------------------------------------------------------------
+// 4. per-tile depth order
+// ---------------------------------------------------------------------------
+struct SortSmem {
+    uint32_t key[kChunk];
+    uint32_t val[kChunk];
+    uint16_t cnt[kItems * 4][kRadix];
+    uint32_t base[kRadix];
+    uint32_t tmp[4];
+    uint32_t band, bor;
+};
+
+__device__ __forceinline__ uint64_t tile_key(uint32_t t, uint32_t depth_bits)
+{
+    return ((uint64_t)t << 32) | (uint64_t)depth_bits;
+}
+
+// Stable ranks inside one chunk of up to kChunk keys held striped: key[r] is
+// item r * 256 + tid, present when that is below n.  Afterwards
+// s.cnt[r * 4 + w][d] is the number of keys of digit d in the (round, wave)
+// groups before (r, w), rank[r] the position of item r among the keys of its
+// digit in its own group, and the result the chunk's count of digit `tid`.
+__device__ uint32_t rank_chunk(const uint32_t (&key)[kItems], int n, int shift, SortSmem& s,
+                               uint32_t (&rank)[kItems])
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int slots = ((n + kBlock - 1) / kBlock) * 4;
+    for (int q = 0; q < slots; ++q) s.cnt[q][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (r * kBlock < n) {   // the same for the whole block
+            const bool ok = r * kBlock + tid < n;
+            const uint32_t d = (key[r] >> shift) & 0xffu;
+            uint64_t m = __ballot(ok);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool set = (d >> bit) & 1u;
+                const uint64_t bal = __ballot(set);
+                m &= set ? bal : ~bal;
+            }
+            rank[r] = (uint32_t)__popcll(m & lt);
+            if (ok && (m & lt) == 0ull) s.cnt[r * 4 + w][d] = (uint16_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+    uint32_t run = 0;
+    for (int q = 0; q < slots; ++q) {
+        const uint32_t c = s.cnt[q][tid];
+        s.cnt[q][tid] = (uint16_t)run;
+        run += c;
+    }
+    __syncthreads();
+    return run;
+}
+
+// The bits in which the keys of the tile differ (block-wide AND / OR).
+__device__ uint32_t varying_bits(uint32_t a, uint32_t o, SortSmem& s)
+{
+    if (threadIdx.x == 0) {
+        s.band = ~0u;
+        s.bor = 0u;
+    }
+    __syncthreads();
+    atomicAnd(&s.band, a);
+    atomicOr(&s.bor, o);
+    __syncthreads();
+    const uint32_t diff = s.band ^ s.bor;
+    __syncthreads();
+    return diff;
+}
+
+// L <= kChunk: keys in registers, exchanged through LDS after every pass.
+__device__ void sort_tile_small(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
+                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
+                                SortSmem& sm)
+{
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint32_t key[kItems], val[kItems], rank[kItems];
+    uint32_t a = ~0u, o = 0u;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int j = r * kBlock + tid;
+        key[r] = 0u;
+        val[r] = 0u;
+        rank[r] = 0u;
+        if (j < L) {
+            val[r] = vals[s0 + j];
+            key[r] = __float_as_uint(depth[val[r]]);   // positive floats order as unsigned ints
+            a &= key[r];
+            o |= key[r];
+        }
+    }
+    const uint32_t diff = varying_bits(a, o, sm);
+    bool moved = false;
+    for (int p = 0; p < 4; ++p) {
+        const int shift = 8 * p;
+        if (((diff >> shift) & 0xffu) == 0u) continue;   // one digit value: order unchanged
+        moved = true;
+        const uint32_t cnt = rank_chunk(key, L, shift, sm, rank);
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_scan(cnt, tot, sm.tmp);
+        sm.base[tid] = pre;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int j = r * kBlock + tid;
+            if (j < L) {
+                const uint32_t d = (key[r] >> shift) & 0xffu;
+                const uint32_t pos = sm.base[d] + sm.cnt[r * 4 + w][d] + rank[r];
+                sm.key[pos] = key[r];
+                sm.val[pos] = val[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int j = r * kBlock + tid;
+            if (j < L) {
+                key[r] = sm.key[j];
+                val[r] = sm.val[j];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int j = r * kBlock + tid;
+        if (j < L) {
+            if (moved) vals[s0 + j] = val[r];
+            if (keys) keys[s0 + j] = tile_key(t, key[r]);
+        }
+    }
+}
+
+// L > kChunk: each pass histograms the whole tile, then scatters it chunk by
+// chunk in order between two global buffers (k1/v1, k0/v0 at the tile's own
+// offsets); the last pass writes vals.  A single pass goes through k1/v1 and
+// is copied back, so no pass reads and writes the same buffer.
+__device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float* depth,
+                                uint32_t* vals, uint64_t* keys, uint32_t* k0, uint32_t* v0,
+                                uint32_t* k1, uint32_t* v1, SortSmem& sm)
+{
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint32_t a = ~0u, o = 0u;
+    for (int64_t j = tid; j < L; j += kBlock) {
+        const uint32_t k = __float_as_uint(depth[vals[s0 + j]]);
+        a &= k;
+        o |= k;
+    }
+    const uint32_t diff = varying_bits(a, o, sm);
+    uint32_t pmask = 0;   // digits that need a pass
+    for (int p = 0; p < 4; ++p)
+        if (((diff >> (8 * p)) & 0xffu) != 0u) pmask |= 1u << p;
+    const int np = __popc(pmask);
+    if (np == 0) {
+        if (keys)
+            for (int64_t j = tid; j < L; j += kBlock)
+                keys[s0 + j] = tile_key(t, __float_as_uint(depth[vals[s0 + j]]));
+        return;
+    }
+    const uint32_t* sk = nullptr;   // null: keys gathered from depth
+    const uint32_t* sv = vals + s0;
+    for (int p = 0, q = 0; p < 4; ++p) {
+        if (((pmask >> p) & 1u) == 0u) continue;
+        const int shift = 8 * p;
+        const bool last = q == np - 1 && np > 1;
+        uint32_t* dk = last ? nullptr : ((q & 1) ? k0 : k1) + s0;
+        uint32_t* dv = last ? vals + s0 : ((q & 1) ? v0 : v1) + s0;
+        sm.base[tid] = 0u;
+        __syncthreads();
+        for (int64_t j = tid; j < L; j += kBlock) {
+            const uint32_t k = sk ? sk[j] : __float_as_uint(depth[sv[j]]);
+            atomicAdd(&sm.base[(k >> shift) & 0xffu], 1u);
+        }
+        __syncthreads();
+        const uint32_t h = sm.base[tid];
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_scan(h, tot, sm.tmp);
+        sm.base[tid] = pre;
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < L; c0 += kChunk) {
+            const int n = (int)min<int64_t>(kChunk, L - c0);
+            uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const int j = r * kBlock + tid;
+                key[r] = 0u;
+                val[r] = 0u;
+                rank[r] = 0u;
+                if (j < n) {
+                    val[r] = sv[c0 + j];
+                    key[r] = sk ? sk[c0 + j] : __float_as_uint(depth[val[r]]);
+                }
+            }
+            const uint32_t cnt = rank_chunk(key, n, shift, sm, rank);
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const int j = r * kBlock + tid;
+                if (j < n) {
+                    const uint32_t d = (key[r] >> shift) & 0xffu;
+                    const uint32_t pos = sm.base[d] + sm.cnt[r * 4 + w][d] + rank[r];
+                    if (dk) dk[pos] = key[r];
+                    dv[pos] = val[r];
+                    if (last && keys) keys[s0 + pos] = tile_key(t, key[r]);
+                }
+            }
+            __syncthreads();
+            sm.base[tid] += cnt;
+            __syncthreads();
+        }
+        sk = dk;
+        sv = dv;
+        ++q;
+    }
+    if (np == 1)
+        for (int64_t j = tid; j < L; j += kBlock) {
+            vals[s0 + j] = v1[s0 + j];
+            if (keys) keys[s0 + j] = tile_key(t, k1[s0 + j]);
+        }
+}
+
+// ---- one wave per tile (L <= kWaveMax) ------------------------------------
+constexpr int kWaveItems = kWaveMax / 64;   // entries per lane
+
+struct WaveSmem {
+    uint32_t key[kWaveMax];
+    uint32_t val[kWaveMax];
+    uint32_t off[kRadix];
+};
+
+union TileSortSmem {
+    SortSmem blk;
+    WaveSmem wave[kBlock / 64];
+};
+
+// Orders the wave's LDS accesses against each other without a workgroup
+// barrier (the other waves of the workgroup sort other tiles).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stable LSD radix sort of one tile's L <= kWaveMax entries by one wave.
+// Entry r * 64 + lane sits in key[r] / val[r].  Per 8-bit pass: the lanes of
+// a round that share a digit are found with 8 ballots; their leader adds the
+// group size to the digit's count; the counts are scanned; the rounds are
+// then replayed in order, each entry going to its digit's running offset
+// plus its rank in the group.
+__device__ void sort_tile_wave(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
+                               uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
+                               WaveSmem& sm)
+{
+    const int lane = threadIdx.x & 63;
+    const int R = (L + 63) >> 6;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[kWaveItems], val[kWaveItems], info[kWaveItems];
+    uint32_t a = ~0u, o = 0u;
+#pragma unroll
+    for (int r = 0; r < kWaveItems; ++r) {
+        const int j = r * 64 + lane;
+        key[r] = 0u;
+        val[r] = 0u;
+        info[r] = 0u;
+        if (j < L) {
+            val[r] = vals[s0 + j];
+            key[r] = __float_as_uint(depth[val[r]]);   // positive floats order as unsigned ints
+            a &= key[r];
+            o |= key[r];
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a &= __shfl_xor(a, d, 64);
+        o |= __shfl_xor(o, d, 64);
+    }
+    const uint32_t diff = a ^ o;   // the bits in which the keys differ
+    bool moved = false;
+    for (int p = 0; p < 4; ++p) {
+        const int shift = 8 * p;
+        if (((diff >> shift) & 0xffu) == 0u) continue;   // one digit value: order unchanged
+        moved = true;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sm.off[c * 64 + lane] = 0u;
+        wave_sync();
+        // digit counts; info = rank in its group | group size << 8 | leader << 16
+#pragma unroll
+        for (int r = 0; r < kWaveItems; ++r) {
+            if (r < R) {   // the same for the whole wave
+                const bool ok = r * 64 + lane < L;
+                const uint32_t d = (key[r] >> shift) & 0xffu;
+                uint64_t m = __ballot(ok);
+#pragma unroll
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool set = (d >> bit) & 1u;
+                    const uint64_t bal = __ballot(set);
+                    m &= set ? bal : ~bal;
+                }
+                const uint32_t rank = (uint32_t)__popcll(m & lt);
+                const uint32_t size = (uint32_t)__popcll(m);
+                const bool leader = ok && rank == 0u;
+                info[r] = rank | (size << 8) | (leader ? 1u << 16 : 0u);
+                if (leader) atomicAdd(&sm.off[d], size);
+            }
+        }
+        wave_sync();
+        // exclusive scan of the 256 counts, four consecutive digits per lane
+        {
+            uint32_t c4[4], sum = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                c4[c] = sm.off[4 * lane + c];
+                sum += c4[c];
+            }
+            uint32_t inc = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += y;
+            }
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sm.off[4 * lane + c] = run;
+                run += c4[c];
+            }
+        }
+        wave_sync();
+        // replay the rounds in order
+#pragma unroll
+        for (int r = 0; r < kWaveItems; ++r) {
+            if (r < R) {
+                const int j = r * 64 + lane;
+                const uint32_t d = (key[r] >> shift) & 0xffu;
+                if (j < L) {
+                    const uint32_t pos = sm.off[d] + (info[r] & 0xffu);
+                    sm.key[pos] = key[r];
+                    sm.val[pos] = val[r];
+                }
+                wave_sync();   // every lane has read the offsets of this round
+                if (info[r] >> 16) sm.off[d] += (info[r] >> 8) & 0xffu;
+                wave_sync();
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kWaveItems; ++r) {
+            const int j = r * 64 + lane;
+            if (j < L) {
+                key[r] = sm.key[j];
+                val[r] = sm.val[j];
+            }
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int r = 0; r < kWaveItems; ++r) {
+        const int j = r * 64 + lane;
+        if (j < L) {
+            if (moved) vals[s0 + j] = val[r];
+            if (keys) keys[s0 + j] = tile_key(t, key[r]);
+        }
+    }
+}
+
+// Tiles taken in `order` (longest first); the first n_long of them are longer
+// than kWaveMax and get a whole workgroup each (registers + LDS up to kChunk
+// entries, global ping-pong beyond); every later workgroup gives each of its
+// four waves one tile.  The instances of a tile arrive in index order; they
+// leave in (depth, index) order, with their 64-bit keys when keys is set.
+__global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ n_long,
+                                                   int num_tiles,
+                                                   const uint32_t* __restrict__ d_tiles,
+                                                   const float* __restrict__ depth,
+                                                   uint32_t* __restrict__ vals,
+                                                   uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ k0,
+                                                   uint32_t* __restrict__ v0,
+                                                   uint32_t* __restrict__ k1,
+                                                   uint32_t* __restrict__ v1)
+{
+    __shared__ TileSortSmem sm;
+    const uint32_t n = d_tiles ? min(*d_tiles, (uint32_t)num_tiles) : (uint32_t)num_tiles;
+    const uint32_t nl = min(*n_long, n);
+    uint32_t idx;
+    if (blockIdx.x < nl) {
+        idx = blockIdx.x;
+    } else {
+        idx = nl + (blockIdx.x - nl) * (kBlock / 64) + (threadIdx.x >> 6);
+        if (idx >= n) return;   // whole waves leave; no workgroup barrier follows
+    }
+    const uint32_t t = order[idx];
+    if (t >= (uint32_t)num_tiles) return;
+    const uint32_t s0 = ranges[2 * t];
+    const int64_t L = (int64_t)ranges[2 * t + 1] - (int64_t)s0;
+    if (blockIdx.x < nl) {   // the whole workgroup
+        if (L <= kChunk)
+            sort_tile_small((int)L, s0, t, depth, vals, keys, sm.blk);
+        else
+            sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
+    } else if (L == 1) {
+        if (keys && (threadIdx.x & 63) == 0)
+            keys[s0] = tile_key(t, __float_as_uint(depth[vals[s0]]));
+    } else if (L > 1 && L <= kWaveMax) {
+        sort_tile_wave((int)L, s0, t, depth, vals, keys, sm.wave[threadIdx.x >> 6]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -523,26 +903,15 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     uint32_t* d_sortn = ws.ctl;         // min(M, capacity)
 
     launch_fill_u32(out.ranges, 2 * (int64_t)num_tiles, 0u, stream);
-    // 1. compaction (N, or *d_n entries when given)
-    hipLaunchKernelGGL(k_count_visible, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, N,
-                       d_n, ws.blk);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk, d_n, N, d_Nv,
-                       (uint32_t*)nullptr, (uint64_t)0, (uint32_t*)nullptr);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, depth, N,
-                       d_n, ws.blk, ws.dk[0], ws.dv[0]);
-    // 2. depth order of the visible triangles (stable: index order kept on ties)
-    hipError_t err = radix_sort(ws.dk[0], ws.dv[0], ws.dk[1], ws.dv[1], ws.dk[0], ws.dv[0], d_Nv,
-                                N, 32, ws, stream);
-    if (err != hipSuccess) return err;
-    // 3. instance offsets and emission in depth order
-    hipLaunchKernelGGL(k_count_instances, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles,
-                       ws.dv[0], d_Nv, ws.blk);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk, d_Nv, (int64_t)0,
-                       d_M, d_sortn, out.capacity, d_ovf);
+    // 1. tile counts of the N (or *d_n) entries in index order
+    hipLaunchKernelGGL(k_count, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, N, d_n,
+                       ws.blk, ws.blk_vis);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk, d_n, N, d_M,
+                       d_sortn, out.capacity, d_ovf, (const uint32_t*)ws.blk_vis, d_Nv);
     int64_t m_max = (int64_t)out.capacity;
     if (h_count) {
-        err = hipMemcpyAsync(h_count, out.d_count, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                             stream);
+        hipError_t err = hipMemcpyAsync(h_count, out.d_count, 2 * sizeof(uint32_t),
+                                        hipMemcpyDeviceToHost, stream);
         if (err != hipSuccess) return err;
         err = hipStreamSynchronize(stream);
         if (err != hipSuccess) return err;
@@ -555,17 +924,26 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
         }
         m_max = h_count[0];
     }
+    // 2. instances in index order
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles,
-                       reinterpret_cast<const short4*>(rect), ws.dv[0], d_Nv, ws.blk, tiles_x,
-                       views, per_view, out.capacity, ws.tk[0], ws.tv[0]);
-    // 4. stable sort by tile
-    err = radix_sort(ws.tk[0], ws.tv[0], ws.tk[1], ws.tv[1], ws.tfin, out.vals, d_sortn, m_max,
-                     bits_for(num_tiles), ws, stream);
+                       reinterpret_cast<const short4*>(rect), N, d_n, ws.blk, tiles_x, views,
+                       per_view, out.capacity, ws.tk[0], ws.tv[0]);
+    // 3. stable sort by tile, ranges, longest-first tile order
+    hipError_t err = radix_sort(ws.tk[0], ws.tv[0], ws.tk[1], ws.tv[1], ws.tfin, out.vals,
+                                d_sortn, m_max, bits_for(num_tiles), ws, stream);
     if (err != hipSuccess) return err;
     if (m_max > 0)
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((m_max + 255) / 256)), dim3(256), 0, stream,
-                           ws.tfin, out.vals, depth, d_sortn, out.ranges, out.keys);
-    launch_tile_order(out.ranges, num_tiles, d_tiles, out.order, stream);
+                           ws.tfin, d_sortn, out.ranges);
+    uint32_t* order = out.order ? out.order : ws.torder;
+    uint32_t* n_long = ws.ctl + 1;
+    launch_tile_order(out.ranges, num_tiles, d_tiles, order, stream, n_long);
+    // 4. depth order inside every tile
+    if (m_max > 0 && num_tiles > 0)
+        hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)num_tiles), dim3(kBlock), 0, stream,
+                           out.ranges, (const uint32_t*)order, (const uint32_t*)n_long, num_tiles,
+                           d_tiles, depth, out.vals, out.keys, ws.tk[0], ws.tv[0], ws.tk[1],
+                           ws.tv[1]);
     return hipGetLastError();
 }
 

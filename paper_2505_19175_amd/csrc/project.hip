@@ -118,10 +118,11 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
     // Tight region {o I >= alpha_min} = {u >= u_min}: the triangle scaled
     // about its incentre by 1 - u_min, u_min = (alpha_min/o)^(1/sigma).
     int px0 = 0, px1 = -1, py0 = 0, py1 = -1;
+    double umin = 0.0;
     if (vis) {
         const double sx = (g.len[1] * g.q[0][0] + g.len[2] * g.q[1][0] + g.len[0] * g.q[2][0]) / g.P;
         const double sy = (g.len[1] * g.q[0][1] + g.len[2] * g.q[1][1] + g.len[0] * g.q[2][1]) / g.P;
-        const double umin = pow((double)cfg.alpha_min / (double)oi, 1.0 / (double)si);
+        umin = pow((double)cfg.alpha_min / (double)oi, 1.0 / (double)si);
         const double f = 1.0 - umin;
         double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
 #pragma unroll
@@ -160,13 +161,17 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
         R.B[k] = w * g.e[k][0];
         R.C[k] = w * (g.e[k][0] * (0.5 - qy) - g.e[k][1] * (0.5 - qx));
     }
-    R.ax = px0;
-    R.ay = py0;
+    R.ax = (int16_t)px0;
+    R.ay = (int16_t)py0;
     R.o = oi;
     R.sigma = si;
     R.z = (float)zc;
     R.px0 = (int16_t)px0; R.px1 = (int16_t)px1; R.py0 = (int16_t)py0; R.py1 = (int16_t)py1;
     R.tri = (uint32_t)tri;
+    // A pixel with u below u_min (1 - 2^-10) cannot reach alpha_min through the
+    // FP32 window (its error is orders of magnitude below that margin);
+    // rounded toward zero so the bound stays below u_min.
+    R.ut = __double2float_rz(umin * (1.0 - 1.0 / 1024.0));
     R.pad[0] = R.pad[1] = R.pad[2] = 0.f;
 
     // colour: real SH along the view direction, + 1/2, clamped at zero

@@ -7,14 +7,14 @@
 // g = l >> 4 = (g & 1, g >> 1).
 //
 // The tile's list is walked in batches of 256 entries staged through LDS:
-// each thread copies one record as seven 16-byte chunks into chunk-major
-// arrays (consecutive lanes write consecutive slots: no bank conflicts) and
-// marks the 4x4 blocks of the tile its tight box touches.  Every row of a
-// wave then walks its own list of entries -- the ones touching its block --
-// so one wave step advances four lists at once.  Triangles here cover a few
-// pixels, so per-block lists are ~2.4x shorter per step than one list for
-// the whole 8x8 quadrant.  List heads are popped with scalar bit scans of
-// ballot masks; each lane reads its row's record from LDS.
+// each thread copies one record as six 16-byte chunks and its depth into
+// chunk-major arrays (consecutive lanes write consecutive slots: no bank
+// conflicts) and marks the 4x4 blocks of the tile that can hold a pixel it
+// composites.  Each wave then writes, for each of its four blocks, the byte
+// indices of the batch entries marked for it (ballot + mbcnt compaction), so
+// every row walks its own list -- one wave step advances four lists, and a
+// row never evaluates a triangle that misses its block.  The lists live in
+// LDS and are read one byte per lane per step: no scalar list bookkeeping.
 //
 // The window is evaluated as three FP64 affine functions per pixel (gfx950
 // issues v_fma_f64 at the rate of unpacked v_fma_f32); the rest is FP32,
@@ -25,12 +25,13 @@
 namespace ts {
 
 constexpr int kBatch = kBlock;   // entries staged per batch
-constexpr int kChunks = 7;       // 16-byte chunks of a record the raster reads
-constexpr int kMasks = kBatch / 64;
+constexpr int kChunks = 6;       // 16-byte chunks of a record the raster reads (+ z)
 
 struct Stage {
     float4 q[kChunks][kBatch];
-    uint16_t hit[kBatch];        // bit 4 w + g: touches block g of quadrant w
+    float z[kBatch];
+    uint16_t hit[kBatch];        // bit 4 w + g: may composite in block g of quadrant w
+    uint8_t list[16][kBatch];    // per block 4 w + g: its entries of the batch, in order
 };
 
 union RecView {
@@ -39,16 +40,23 @@ union RecView {
 };
 
 // Copy record `tri` into LDS slot threadIdx.x and return the mask of the
-// tile's sixteen 4x4 blocks its tight box touches.
+// tile's sixteen 4x4 blocks that may hold a composited pixel of it: the
+// tight box touches the block, and for every edge k the largest u_k over the
+// block's pixel centres (at one corner, u_k being affine) reaches ut, the
+// lower bound of u over pixels that composite.  The box and the three edge
+// tests are the separating axes of the tight region (a triangle) and the
+// block's square of pixel centres.  The slack covers the rounding of this
+// evaluation and of the per-pixel one, so no pixel that composites is lost.
 __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restrict__ rec,
                                               uint32_t tri, int tx0, int ty0)
 {
     const float4* src = reinterpret_cast<const float4*>(rec + tri);
     RecView u;
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) u.q[c] = src[c];
+    for (int c = 0; c < 8; ++c) u.q[c] = src[c];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = u.q[c];
+    S.z[threadIdx.x] = u.r.z;
     uint32_t cx = 0, cy = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -56,13 +64,44 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
         cx |= (u.r.px0 <= x0 + 3 && u.r.px1 >= x0) ? (1u << i) : 0u;
         cy |= (u.r.py0 <= y0 + 3 && u.r.py1 >= y0) ? (1u << i) : 0u;
     }
+    uint32_t box = 0;   // bit 4 by + bx
+#pragma unroll
+    for (int by = 0; by < 4; ++by) box |= ((cy >> by) & 1u) ? (cx << (4 * by)) : 0u;
+
+    const double dx0 = (double)(tx0 - u.r.ax), dy0 = (double)(ty0 - u.r.ay);
+    const double ut = (double)u.r.ut;
+    // coefficients read back from this thread's own LDS slot, one edge at a
+    // time, to keep the register peak of the staging step low
+    const double* cf = reinterpret_cast<const double*>(&S.q[0][0]);
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        auto coef = [&](int idx) {   // double idx of the record: chunk idx / 2, half idx % 2
+            return cf[2 * (size_t)((idx >> 1) * kBatch + threadIdx.x) + (idx & 1)];
+        };
+        const double A = coef(k), B = coef(3 + k), C = coef(6 + k);
+        const double cxk = dx0 + (A > 0.0 ? 3.0 : 0.0), cyk = dy0 + (B > 0.0 ? 3.0 : 0.0);
+        const double base = fma(A, cxk, fma(B, cyk, C));   // largest u_k over block (0, 0)
+        const double slack = 0x1p-46 * (fabs(C) + fabs(A) * (fabs(dx0) + 16.0) +
+                                        fabs(B) * (fabs(dy0) + 16.0));
+        const double lim = ut - slack;
+        const double A4 = 4.0 * A, B4 = 4.0 * B;
+#pragma unroll 1
+        for (int by = 0; by < 4; ++by) {
+            const double rb = fma(B4, (double)by, base);
+#pragma unroll
+            for (int bx = 0; bx < 4; ++bx) {
+                const double val = fma(A4, (double)bx, rb);
+                box &= val >= lim ? ~0u : ~(1u << (4 * by + bx));
+            }
+        }
+    }
     uint32_t m = 0;
 #pragma unroll
     for (int by = 0; by < 4; ++by)
 #pragma unroll
         for (int bx = 0; bx < 4; ++bx) {
             const int w = (bx >> 1) + 2 * (by >> 1), g = (bx & 1) + 2 * (by & 1);
-            m |= (((cx >> bx) & (cy >> by)) & 1u) << (4 * w + g);
+            m |= ((box >> (4 * by + bx)) & 1u) << (4 * w + g);
         }
     return m;
 }
@@ -72,66 +111,47 @@ __device__ __forceinline__ TriRecord read_rec(const Stage& S, int j)
     RecView u;
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) u.q[c] = S.q[c][j];
-    u.q[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+    u.r.z = S.z[j];
     return u.r;
 }
 
-// One row's entry list of the current batch: bit b of word c set when entry
-// 64 c + b touches the row's block.  Wave-uniform, kept in scalar registers.
-struct List {
-    uint64_t m0, m1, m2, m3;
+// Write the entry lists of the wave's four blocks for a batch of n entries:
+// S.list[4 w + g] receives, in increasing order, the entries e < lim_g whose
+// mark for block g is set.  Returns the four lengths (wave-uniform).
+struct Lens {
+    int n0, n1, n2, n3;
 };
-static_assert(kMasks == 4, "List holds four 64-entry words");
 
-// Lists of the four rows of wave w.
-__device__ __forceinline__ void row_lists(const uint16_t* s_hit, int n, int w, int lane,
-                                          List& L0, List& L1, List& L2, List& L3)
+__device__ __forceinline__ Lens build_lists(Stage& S, int n, int w, int lane, int lim0,
+                                            int lim1, int lim2, int lim3)
 {
-    uint32_t h[4];
+    Lens L{0, 0, 0, 0};
+    uint8_t* l0 = S.list[4 * w];
+    uint8_t* l1 = S.list[4 * w + 1];
+    uint8_t* l2 = S.list[4 * w + 2];
+    uint8_t* l3 = S.list[4 * w + 3];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int j = c * 64 + lane;
-        h[c] = j < n ? (uint32_t)s_hit[j] >> (4 * w) : 0u;
+    for (int c = 0; c < kBatch / 64; ++c) {
+        const int e = c * 64 + lane;
+        const uint32_t h = e < n ? ((uint32_t)S.hit[e] >> (4 * w)) & 0xfu : 0u;
+        auto put = [&](bool bit, uint8_t* lst, int& len) {
+            const uint64_t m = __ballot(bit);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (bit) lst[len + (int)below] = (uint8_t)e;
+            len += __popcll(m);
+        };
+        put((h & 1u) && e < lim0, l0, L.n0);
+        put((h & 2u) && e < lim1, l1, L.n1);
+        put((h & 4u) && e < lim2, l2, L.n2);
+        put((h & 8u) && e < lim3, l3, L.n3);
     }
-    L0 = {__ballot(h[0] & 1u), __ballot(h[1] & 1u), __ballot(h[2] & 1u), __ballot(h[3] & 1u)};
-    L1 = {__ballot(h[0] & 2u), __ballot(h[1] & 2u), __ballot(h[2] & 2u), __ballot(h[3] & 2u)};
-    L2 = {__ballot(h[0] & 4u), __ballot(h[1] & 4u), __ballot(h[2] & 4u), __ballot(h[3] & 4u)};
-    L3 = {__ballot(h[0] & 8u), __ballot(h[1] & 8u), __ballot(h[2] & 8u), __ballot(h[3] & 8u)};
-}
-
-// Remove and return the first (last) entry of a list; -1 when it is empty.
-__device__ __forceinline__ int pop_front(List& L)
-{
-    int b;
-    if (L.m0) { b = __builtin_ctzll(L.m0); L.m0 &= L.m0 - 1ull; return b; }
-    if (L.m1) { b = __builtin_ctzll(L.m1); L.m1 &= L.m1 - 1ull; return 64 + b; }
-    if (L.m2) { b = __builtin_ctzll(L.m2); L.m2 &= L.m2 - 1ull; return 128 + b; }
-    if (L.m3) { b = __builtin_ctzll(L.m3); L.m3 &= L.m3 - 1ull; return 192 + b; }
-    return -1;
-}
-
-__device__ __forceinline__ int pop_back(List& L)
-{
-    int b;
-    if (L.m3) { b = 63 - __builtin_clzll(L.m3); L.m3 &= ~(1ull << b); return 192 + b; }
-    if (L.m2) { b = 63 - __builtin_clzll(L.m2); L.m2 &= ~(1ull << b); return 128 + b; }
-    if (L.m1) { b = 63 - __builtin_clzll(L.m1); L.m1 &= ~(1ull << b); return 64 + b; }
-    if (L.m0) { b = 63 - __builtin_clzll(L.m0); L.m0 &= ~(1ull << b); return b; }
-    return -1;
-}
-
-__device__ __forceinline__ uint64_t below(int lim)   // bits [0, lim) of a word, lim clamped
-{
-    return lim <= 0 ? 0ull : lim >= 64 ? ~0ull : ((1ull << lim) - 1ull);
-}
-
-// Keep only entries j < lim of a list.
-__device__ __forceinline__ void trim(List& L, int lim)
-{
-    L.m0 &= below(lim);
-    L.m1 &= below(lim - 64);
-    L.m2 &= below(lim - 128);
-    L.m3 &= below(lim - 192);
+    // the lists are read by other lanes of this wave only: order the byte
+    // writes before those reads without a workgroup barrier
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return L;
 }
 
 __device__ __forceinline__ int per_row(int g, int j0, int j1, int j2, int j3)
@@ -202,23 +222,21 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         if (tid < n)
             S.hit[tid] = (uint16_t)stage_rec(S, rec, vals[b + tid], J.tx * kTile, J.ty * kTile);
         __syncthreads();
-        List L0, L1, L2, L3;
-        row_lists(S.hit, n, P.w, lane, L0, L1, L2, L3);
-        uint64_t live = __ballot(!done);
-        while (live != 0ull) {
-            // rows whose pixels are all done stop walking their lists
-            if ((live & 0xffffull) == 0ull) trim(L0, 0);
-            if (((live >> 16) & 0xffffull) == 0ull) trim(L1, 0);
-            if (((live >> 32) & 0xffffull) == 0ull) trim(L2, 0);
-            if ((live >> 48) == 0ull) trim(L3, 0);
-            const int j0 = pop_front(L0), j1 = pop_front(L1);
-            const int j2 = pop_front(L2), j3 = pop_front(L3);
-            if ((j0 & j1 & j2 & j3) < 0) break;          // every list is empty
-            const int j = per_row(P.g, j0, j1, j2, j3);
-            const TriRecord r = read_rec(S, j < 0 ? 0 : j);
+        const Lens L = build_lists(S, n, P.w, lane, n, n, n, n);
+        // each lane walks its row's list; a row stops once all its pixels are
+        // done, the wave once no row has work left
+        const int len = per_row(P.g, L.n0, L.n1, L.n2, L.n3);
+        const uint8_t* lst = S.list[4 * P.w + P.g];
+        int jn = lst[0];                 // next entry (read one step ahead)
+        for (int k = 0;; ++k) {
+            const bool act = !done && k < len;
+            if (__ballot(act) == 0ull) break;
+            const int j = jn;
+            jn = lst[k + 1 < kBatch ? k + 1 : 0];
+            const TriRecord r = read_rec(S, j);
             Frag f;
             const double u = frag_alpha(r, P.px - r.ax, P.py - r.ay, cfg.alpha_max, f);
-            const bool contrib = j >= 0 && !done && u > 0.0 && f.a >= cfg.alpha_min;
+            const bool contrib = act && u > 0.0 && f.a >= cfg.alpha_min;
             const float Tn = T * (1.f - f.a);
             const bool stop = contrib && Tn < cfg.T_min;
             const bool comp = contrib && !stop;
@@ -230,7 +248,6 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             T = comp ? Tn : T;
             last = comp ? b - start + (uint32_t)j + 1u : last;
             done = done || stop;
-            live = __ballot(!done);
         }
         if (__syncthreads_and(done)) break;
     }
@@ -415,18 +432,20 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, tx * kTile, ty * kTile);
         }
         __syncthreads();
-        List L0, L1, L2, L3;
-        row_lists(S.hit, n, P.w, lane, L0, L1, L2, L3);
-        trim(L0, rl0 - (int)lo_);
-        trim(L1, rl1 - (int)lo_);
-        trim(L2, rl2 - (int)lo_);
-        trim(L3, rl3 - (int)lo_);
-        for (;;) {
-            const int j0 = pop_back(L0), j1 = pop_back(L1);
-            const int j2 = pop_back(L2), j3 = pop_back(L3);
-            if ((j0 & j1 & j2 & j3) < 0) break;          // every list is empty
-            const int j = per_row(P.g, j0, j1, j2, j3);
-            const int jc = j < 0 ? 0 : j;
+        // entries of this batch each row needs (before its last composited one)
+        const Lens L = build_lists(S, n, P.w, lane, rl0 - (int)lo_, rl1 - (int)lo_,
+                                   rl2 - (int)lo_, rl3 - (int)lo_);
+        const int len = per_row(P.g, L.n0, L.n1, L.n2, L.n3);
+        const int steps = max(max(L.n0, L.n1), max(L.n2, L.n3));
+        const uint8_t* lst = S.list[4 * P.w + P.g];
+        int kn = len - 1;
+        int jn = lst[kn >= 0 ? kn : 0];   // next entry (read one step ahead)
+        for (int st = 0; st < steps; ++st) {   // back to front along each row's list
+            const int k = kn;
+            const int jc = jn;
+            --kn;
+            jn = lst[kn >= 0 ? kn : 0];
+            const int j = k >= 0 ? jc : -1;
             const TriRecord r = read_rec(S, jc);
             const int dx = P.px - r.ax, dy = P.py - r.ay;
             Frag f;

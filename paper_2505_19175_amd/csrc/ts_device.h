@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "ts.h"
@@ -23,19 +24,28 @@ constexpr int kWave = 64;
 // stored in FP64 relative to an integer anchor pixel (ax, ay) so that
 // u_k(p) = A_k dx + B_k dy + C_k with dx = px - ax, dy = py - ay exact
 // integers (the pixel centre's 1/2 is folded into C_k).
+//
+// Byte layout (16-byte chunks): 0-3 A, B, C[0..1]; 4 C[2], anchor, o;
+// 5 sigma, rgb; 6 z, tight box, index; 7 ut.  The rasterizers stage chunks
+// 0-5 and z in LDS.
 struct alignas(16) TriRecord {
     double A[3];
     double B[3];
     double C[3];
-    int32_t ax, ay;
-    float o, sigma;
+    int16_t ax, ay;              // anchor pixel
+    float o;
+    float sigma;
     float rgb[3];
     float z;
     int16_t px0, px1, py0, py1;  // tight pixel box
     uint32_t tri;
+    float ut;     // lower bound of u over the pixels that can composite: u_min (1 - 2^-10)
     float pad[3];
 };
 static_assert(sizeof(TriRecord) == 128, "record must be one 128-byte line");
+static_assert(offsetof(TriRecord, o) == 76 && offsetof(TriRecord, sigma) == 80 &&
+                  offsetof(TriRecord, z) == 96 && offsetof(TriRecord, ut) == 112,
+              "chunk layout the rasterizers stage");
 
 struct Cam {
     float R[9], t[3], fx, fy, cx, cy;

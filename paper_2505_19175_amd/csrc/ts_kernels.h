@@ -35,25 +35,25 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream);
 // order[0..n) = tiles by decreasing list length, n = min(*d_tiles,
 // num_tiles) or num_tiles; nothing when order is null.
 void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
-                       uint32_t* order, hipStream_t stream);
+                       uint32_t* order, hipStream_t stream, uint32_t* n_long = nullptr);
 
 // Workspace carve-up of the binning stage.
 struct BinWorkspace {
-    uint32_t* blk;      // [nbN + 1] block sums / offsets
-    uint32_t* dk[2];    // [N] depth keys (ping-pong)
-    uint32_t* dv[2];    // [N] triangle ids (ping-pong)
-    uint32_t* off;      // [N] first instance of each depth-sorted triangle
+    uint32_t* blk;      // [nbN + 1] per-block instance counts / offsets
+    uint32_t* blk_vis;  // [nbN + 1] per-block visible counts
     uint32_t* hist;     // [256][hist_stride] radix block histograms
     uint32_t* dtot;     // [256] radix digit totals
-    uint32_t* tk[2];    // [capacity] tile ids (ping-pong)
-    uint32_t* tv[2];    // [capacity] triangle ids (ping-pong)
+    uint32_t* tk[2];    // [capacity] tile ids (ping-pong; per-tile sort scratch after)
+    uint32_t* tv[2];    // [capacity] entry ids (ping-pong; per-tile sort scratch after)
     uint32_t* tfin;     // [capacity] sorted tile ids
-    uint32_t* ctl;      // [8] device counters: [0] sort count min(M, capacity)
+    uint32_t* torder;   // [num_tiles] tile order when the caller keeps none
+    uint32_t* ctl;      // [8] device counters: [0] sort count min(M, capacity),
+                        //     [1] tiles too long for the one-wave sort
     int64_t hist_stride;
     size_t bytes;
 };
 
-BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity);
+BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity, int64_t num_tiles);
 
 // Device-side binning of N entries (or *d_n <= N when d_n is set).  With
 // views set, entry e belongs to view e / per_view and its tiles are offset

@@ -166,6 +166,54 @@ def test_mid_bins_bit_exact():
     _check_bins(st, scene, cam, cfg)
 
 
+def _one_tile_soup(seed, n, mode):
+    """n small triangles whose tight boxes all fall in tile (1, 1) of a 64x64
+    image, every triangle flat at depth z (so its depth key is exactly z).
+    mode: 'equal' (one key), 'ulps' (keys 3.0 + 0..199 ulps: only the low
+    byte differs), 'spread' (z in [2, 4) with repeats), 'wide' (z in [0.5, 40))."""
+    rng = np.random.default_rng(seed)
+    W = H = 64
+    cam = synth.identity_camera(W, H)
+    f, c = float(cam.fx), float(cam.cx)
+    if mode == "equal":
+        z = np.full(n, 3.0, np.float32)
+    elif mode == "ulps":
+        z = (np.float32(3.0).view(np.uint32) + rng.integers(0, 200, n).astype(np.uint32)).view(np.float32)
+    elif mode == "spread":
+        z = rng.uniform(2.0, 4.0, n).astype(np.float32)
+        rep = rng.random(n) < 0.2
+        z[rep] = z[rng.integers(0, n, int(rep.sum()))]
+    else:
+        z = rng.uniform(0.5, 40.0, n).astype(np.float32)
+    ctr = rng.uniform(21.0, 26.0, (n, 2))
+    ang = rng.uniform(0, 2 * np.pi, n)[:, None] + np.array([0.0, 2.0944, 4.1888])[None, :]
+    px = ctr[:, None, 0] + 2.5 * np.cos(ang)
+    py = ctr[:, None, 1] + 2.5 * np.sin(ang)
+    v = np.stack([(px - c) * z[:, None] / f, (py - c) * z[:, None] / f,
+                  np.repeat(z[:, None], 3, 1)], -1).astype(np.float32)
+    sc = synth.Scene(v, np.full(n, 0.9, np.float32), np.ones(n, np.float32),
+                     rng.uniform(0, 1, (n, 1, 3)).astype(np.float32))
+    return sc, cam
+
+
+@pytest.mark.parametrize("n,mode", [(2, "spread"), (65, "wide"), (700, "equal"), (1024, "spread"),
+                                    (1024, "ulps"), (1025, "ulps"), (1500, "equal"),
+                                    (2048, "spread"), (2049, "spread"), (5000, "equal"),
+                                    (5000, "ulps"), (5000, "spread"), (4500, "wide")])
+def test_bins_one_deep_tile(n, mode):
+    """The per-tile depth sort in its three forms (one wave up to 1024
+    entries, a workgroup in registers up to 2048, global ping-pong beyond)
+    and with 0, 1, 3 and 4 digit passes; ties keep index order.  Bit-exact
+    against the oracle's stable sort."""
+    sc, cam = _one_tile_soup(61, n, mode)
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    ref = O.bin_instances(sc, cam, cfg)
+    lens = ref["ranges"][:, 1] - ref["ranges"][:, 0]
+    assert lens.max() == n == ref["count"]          # one tile holds every triangle
+    _check_bins(st, sc, cam, cfg)
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
