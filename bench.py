@@ -13,6 +13,7 @@ gradient resident in HBM.  Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,8 +28,52 @@ P_REC = 48      # minimum raster record: 2D vertices, o, sigma, rgb, z (bytes)
 G_REC = 48      # 2D gradient record (bytes)
 
 
+# HBM traffic of one launch of a kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of `bench.py --steps 2 --warmup 1 --no-cpu-baseline
+# --no-serve` (KiB per dispatch), each scaled by what the same counter reads
+# for a 512 MiB device copy (`bench.py --copy-probe`: FETCH_SIZE reads half
+# the copied bytes, WRITE_SIZE all of them).  Valid only for the kernel
+# source the counters were taken on: `src` is the SHA-256 of that file.
+TRAFFIC = {
+    "project_bwd": {"file": "paper_2505_19175_amd/csrc/project.hip",
+                    "src": None, "fetch_kib": 2.612e5, "write_kib": 7.949e5,
+                    "fetch_scale": 2.0, "write_scale": 1.0},
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def _sha(path):
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_bytes(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None or t["src"] is None or _sha(t["file"]) != t["src"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def algorithmic_bytes(N, N_v, M, W, H, K, n_upstream=1):
@@ -45,19 +90,22 @@ def algorithmic_bytes(N, N_v, M, W, H, K, n_upstream=1):
 
 
 def cpu_baseline(wl, cam, n_pix, seed=2024):
+    import numpy as np
+
     from oracle import oracle as O
     from paper_2505_19175_amd import synth
     pix = synth.pixel_sample(seed, cam.width, cam.height, n_pix)
     dC, _, _ = synth.upstream(seed + 1, cam.width, cam.height)
     dCs = dC.reshape(3, -1)[:, pix]
     t0 = time.perf_counter()
-    O.render(wl.scene, cam, wl.config, pix=pix)
+    ref = O.render(wl.scene, cam, wl.config, pix=pix)
     O.backward(wl.scene, cam, wl.config, dCs, pix=pix)
     dt = time.perf_counter() - t0
-    return {"value": round(n_pix / dt / 1e6, 6), "unit": "Mpixel/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"{n_pix} seeded pixels of the same view, forward + backward "
-                      f"(FP64 brute force over all triangles), {dt:.1f} s"}
+    res = {"value": round(n_pix / dt / 1e6, 6), "unit": "Mpixel/s", "cores": O.threads(),
+           "kind": "oracle",
+           "sample": f"{n_pix} seeded pixels of the same view, forward + backward "
+                     f"(FP64 brute force over all triangles), {dt:.1f} s"}
+    return res, float(np.mean(ref["nfrag"]))
 
 
 def serve_bench(rates, duration, warmup, seed=5):

@@ -109,6 +109,11 @@ typedef struct ts_bins {
     uint64_t capacity;  /* entries available in keys / vals */
     uint32_t* order;    /* [tiles] tiles by decreasing list length (the order in which
                            the rasterizers take them); may be NULL: natural order */
+    uint16_t* blocks;   /* [capacity] per instance, bit 4 q + b: the 4x4 pixel block b of
+                           8x8 quadrant q of its tile holds a pixel where the instance
+                           was composited; written by ts_render_forward, read by the
+                           backward to skip the blocks where it contributed nothing
+                           (2 bytes per instance, not per fragment); may be NULL */
 } ts_bins;
 
 /* Bytes of one raster record (the layout is private to the library). */
@@ -158,6 +163,9 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
  * Outputs (device, [H][W] unless noted): rgb [3][H][W], alpha, depth,
  * T_final (transmittance left), last (number of list entries of the pixel's
  * tile up to and including its last composited fragment; backward state).
+ * When bins->blocks is set it also receives, per list entry, the 4x4 blocks
+ * where that entry was composited (entries after a tile's last composited
+ * one may be left unwritten; the backward never reads them).
  */
 int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
                       const ts_config* cfg, float* rgb, float* alpha, float* depth,
@@ -170,7 +178,8 @@ int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera*
  * proj->g2d, then one thread per triangle chains the 2D gradients to the
  * vertices, opacity, sigma and SH coefficients.
  *   dL_drgb [3][H][W] required; dL_dalpha, dL_ddepth [H][W] may be NULL.
- *   T_final, last: the forward outputs of the same view.
+ *   T_final, last: the forward outputs of the same view; bins->blocks (if
+ *   set) must be the masks that forward wrote into the same bins.
  * Gradients are overwritten (not accumulated); culled triangles get zeros.
  *   gv [N][3][3], go [N], gsigma [N], gsh [N][(deg+1)^2][3]
  */

@@ -54,7 +54,8 @@ class ts_proj(ctypes.Structure):
 class ts_bins(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p),
                 ("ranges", ctypes.c_void_p), ("d_count", ctypes.c_void_p),
-                ("capacity", ctypes.c_uint64), ("order", ctypes.c_void_p)]
+                ("capacity", ctypes.c_uint64), ("order", ctypes.c_void_p),
+                ("blocks", ctypes.c_void_p)]
 
 
 class ts_view(ctypes.Structure):

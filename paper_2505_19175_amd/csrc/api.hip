@@ -153,7 +153,7 @@ int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera*
         return fail(TS_EINVAL, "ts_render_forward: null output");
     ts::launch_raster_forward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
                               to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
-                              rgb, alpha, depth, T_final, last, stream);
+                              rgb, alpha, depth, T_final, last, bins->blocks, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward");
 }
@@ -180,7 +180,8 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
     const ts::Cfg g = to_cfg(cfg);
     ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, k, g,
                                tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), dL_drgb,
-                               dL_dalpha, dL_ddepth, T_final, last, proj->g2d, stream);
+                               dL_dalpha, dL_ddepth, T_final, last, bins->blocks, proj->g2d,
+                               stream);
     ts::launch_backproject(v, sh, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go, gsigma,
                            gsh, stream);
     const hipError_t e = hipGetLastError();
@@ -199,7 +200,8 @@ int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera
     if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_raster_backward: null upstream");
     ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
                                to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
-                               dL_drgb, dL_dalpha, dL_ddepth, T_final, last, proj->g2d, stream);
+                               dL_drgb, dL_dalpha, dL_ddepth, T_final, last, bins->blocks,
+                               proj->g2d, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_raster_backward");
 }

@@ -452,16 +452,26 @@ __global__ __launch_bounds__(256) void k_backproject(
     // dL/dsh[t][k][c] = Y_k(d_t) dL/drgb_c, written as contiguous rows
     float* dst = gsh + base * NSH;
     const int n = nt * NSH;
-    auto val = [&](int f) {
-        const int t = f / NSH, r = f - t * NSH, k = r / 3, c = r - 3 * k;
-        return s_y[t * K + k] * s_g[t * 3 + c];
-    };
-    if ((n & 3) == 0) {
+    if constexpr (NSH % 4 == 0) {
+        constexpr int R4 = NSH / 4;   // float4 per row
         float4* d4 = reinterpret_cast<float4*>(dst);
-        for (int f = tid; f < n / 4; f += 256)
-            d4[f] = make_float4(val(4 * f), val(4 * f + 1), val(4 * f + 2), val(4 * f + 3));
-    } else {
-        for (int f = tid; f < n; f += 256) dst[f] = val(f);
+        if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
+            for (int f = tid; f < n / 4; f += 256) {
+                const int t = f / R4, q0 = 4 * (f - t * R4);
+                float x[4];
+#pragma unroll
+                for (int cq = 0; cq < 4; ++cq) {
+                    const int q = q0 + cq, k = q / 3, ch = q - 3 * k;
+                    x[cq] = s_y[t * K + k] * s_g[t * 3 + ch];
+                }
+                d4[f] = make_float4(x[0], x[1], x[2], x[3]);
+            }
+            return;
+        }
+    }
+    for (int f = tid; f < n; f += 256) {
+        const int t = f / NSH, q = f - t * NSH, k = q / 3, ch = q - 3 * k;
+        dst[f] = s_y[t * K + k] * s_g[t * 3 + ch];
     }
 }
 

@@ -32,6 +32,7 @@ struct Stage {
     float z[kBatch];
     uint16_t hit[kBatch];        // bit 4 w + g: may composite in block g of quadrant w
     uint8_t list[16][kBatch];    // per block 4 w + g: its entries of the batch, in order
+    uint32_t comp[kBatch / 2];   // forward: blocks where each entry composited, 16 bits each
 };
 
 union RecView {
@@ -47,6 +48,15 @@ union RecView {
 // tests are the separating axes of the tight region (a triangle) and the
 // block's square of pixel centres.  The slack covers the rounding of this
 // evaluation and of the per-pixel one, so no pixel that composites is lost.
+__device__ __forceinline__ void stage_copy(Stage& S, const TriRecord* __restrict__ rec,
+                                           uint32_t tri)
+{
+    const float4* src = reinterpret_cast<const float4*>(rec + tri);
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = src[c];
+    S.z[threadIdx.x] = rec[tri].z;
+}
+
 __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restrict__ rec,
                                               uint32_t tri, int tx0, int ty0)
 {
@@ -201,6 +211,7 @@ struct TileJob {
     float* depth;
     float* T;
     uint32_t* last;
+    uint16_t* blocks;   // per list entry: blocks where it composited (null: not kept)
 };
 
 __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
@@ -216,11 +227,13 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     uint32_t last = 0;
     bool done = !inside;
 
+    const uint32_t my_bit = 1u << (4 * P.w + P.g);
     for (uint32_t b = start; b < end; b += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b);
         __syncthreads();
         if (tid < n)
             S.hit[tid] = (uint16_t)stage_rec(S, rec, vals[b + tid], J.tx * kTile, J.ty * kTile);
+        if (tid < kBatch / 2) S.comp[tid] = 0u;
         __syncthreads();
         const Lens L = build_lists(S, n, P.w, lane, n, n, n, n);
         // each lane walks its row's list; a row stops once all its pixels are
@@ -231,7 +244,10 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         for (int k = 0;; ++k) {
             const bool act = !done && k < len;
             if (__ballot(act) == 0ull) break;
-            const int j = jn;
+            // an idle lane reads slot 0 (always staged): a stale slot could hold
+            // non-finite values, and 0 * inf in the branch-free blend is NaN
+            const int jl = jn;              // this step's entry of the row's list
+            const int j = act ? jl : 0;
             jn = lst[k + 1 < kBatch ? k + 1 : 0];
             const TriRecord r = read_rec(S, j);
             Frag f;
@@ -248,8 +264,15 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             T = comp ? Tn : T;
             last = comp ? b - start + (uint32_t)j + 1u : last;
             done = done || stop;
+            if (J.blocks) {   // mark the entry's block if any pixel of the row composited it
+                const uint64_t cm = __ballot(comp);
+                if (P.i == 0 && ((cm >> (16 * P.g)) & 0xffffull) != 0ull)
+                    atomicOr(&S.comp[jl >> 1], my_bit << (16 * (jl & 1)));
+            }
         }
-        if (__syncthreads_and(done)) break;
+        const bool all_done = __syncthreads_and(done);
+        if (J.blocks && tid < n) J.blocks[b + tid] = (uint16_t)(S.comp[tid >> 1] >> (16 * (tid & 1)));
+        if (all_done) break;
     }
     if (inside) {
         const int64_t p = (int64_t)P.py * J.W + P.px;
@@ -268,13 +291,14 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
     int tiles_x, int num_tiles, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
-    float* __restrict__ out_depth, float* __restrict__ out_T, uint32_t* __restrict__ out_last)
+    float* __restrict__ out_depth, float* __restrict__ out_T, uint32_t* __restrict__ out_last,
+    uint16_t* __restrict__ out_blocks)
 {
     __shared__ Stage S;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
     TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
-              ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last};
+              ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last, out_blocks};
     fwd_tile(rec, vals, cfg, J, S);
 }
 
@@ -307,7 +331,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
         const int64_t po = (int64_t)V.pixel_offset;
         TileJob J{(int)(local % V.tiles_x), (int)(local / V.tiles_x), V.cam.width, V.cam.height,
                   ranges[2 * t], ranges[2 * t + 1], out_rgb + 3 * po, out_alpha + po,
-                  out_depth + po, nullptr, nullptr};
+                  out_depth + po, nullptr, nullptr, nullptr};
         fwd_tile(rec, vals, cfg, J, S);
     }
 }
@@ -378,7 +402,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
     int tiles_x, int num_tiles, const float* __restrict__ dL_drgb,
     const float* __restrict__ dL_dalpha, const float* __restrict__ dL_ddepth,
     const float* __restrict__ T_final, const uint32_t* __restrict__ last_in,
-    float* __restrict__ g2d)
+    const uint16_t* __restrict__ blocks, float* __restrict__ g2d)
 {
     __shared__ Stage S;
     __shared__ uint32_t s_tri[kBatch];
@@ -429,7 +453,12 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         if (tid < n) {
             const uint32_t tri = vals[start + lo_ + tid];
             s_tri[tid] = tri;
-            S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, tx * kTile, ty * kTile);
+            if (blocks) {   // the forward's record of where the entry composited
+                stage_copy(S, rec, tri);
+                S.hit[tid] = blocks[start + lo_ + tid];
+            } else {
+                S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, tx * kTile, ty * kTile);
+            }
         }
         __syncthreads();
         // entries of this batch each row needs (before its last composited one)
@@ -442,7 +471,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         int jn = lst[kn >= 0 ? kn : 0];   // next entry (read one step ahead)
         for (int st = 0; st < steps; ++st) {   // back to front along each row's list
             const int k = kn;
-            const int jc = jn;
+            const int jc = k >= 0 ? jn : 0;   // idle lanes read slot 0 (always staged)
             --kn;
             jn = lst[kn >= 0 ? kn : 0];
             const int j = k >= 0 ? jc : -1;
@@ -497,11 +526,11 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                            const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
                            int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
-                           uint32_t* last, hipStream_t stream)
+                           uint32_t* last, uint16_t* blocks, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_raster_fwd, dim3(num_tiles), dim3(kBlock), 0, stream,
                        reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, num_tiles, rgb, alpha, depth, T_final, last);
+                       tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks);
 }
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
@@ -519,11 +548,13 @@ void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_
                             const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
                             int num_tiles, const float* dL_drgb, const float* dL_dalpha,
                             const float* dL_ddepth, const float* T_final,
-                            const uint32_t* last, float* g2d, hipStream_t stream)
+                            const uint32_t* last, const uint16_t* blocks, float* g2d,
+                            hipStream_t stream)
 {
     hipLaunchKernelGGL(k_raster_bwd, dim3(num_tiles), dim3(kBlock), 0, stream,
                        reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, num_tiles, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, g2d);
+                       tiles_x, num_tiles, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, blocks,
+                       g2d);
 }
 
 }  // namespace ts

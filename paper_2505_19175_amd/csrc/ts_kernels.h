@@ -68,7 +68,7 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                            const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
                            int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
-                           uint32_t* last, hipStream_t stream);
+                           uint32_t* last, uint16_t* blocks, hipStream_t stream);
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                                  const uint32_t* order, const ts_view* views,
@@ -81,6 +81,7 @@ void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_
                             int num_tiles,
                             const float* dL_drgb, const float* dL_dalpha,
                             const float* dL_ddepth, const float* T_final,
-                            const uint32_t* last, float* g2d, hipStream_t stream);
+                            const uint32_t* last, const uint16_t* blocks, float* g2d,
+                            hipStream_t stream);
 
 }  // namespace ts

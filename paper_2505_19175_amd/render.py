@@ -61,11 +61,13 @@ class ViewState:
         dev = self.device
         self.vals = torch.empty(self.capacity, dtype=torch.int32, device=dev)
         self.keys = torch.empty(self.capacity, dtype=torch.int64, device=dev) if self.want_keys else None
+        self.blocks = torch.empty(self.capacity, dtype=torch.int16, device=dev)
         self.ws_bytes = B.ts_bin_sort_workspace_bytes(self.N, self.capacity, self.num_tiles)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.bins = B.ts_bins(None if self.keys is None else self.keys.data_ptr(),
                               self.vals.data_ptr(), self.ranges.data_ptr(),
-                              self.d_count.data_ptr(), self.capacity, self.order.data_ptr())
+                              self.d_count.data_ptr(), self.capacity, self.order.data_ptr(),
+                              self.blocks.data_ptr())
 
     def outputs(self) -> Outputs:
         dev, H, W = self.device, self.H, self.W

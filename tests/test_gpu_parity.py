@@ -290,6 +290,25 @@ def test_capacity_growth_and_device_count_mode():
         np.testing.assert_array_equal(a[k], b[k])
 
 
+def test_backward_without_block_masks():
+    """With ts_bins.blocks NULL the forward keeps no masks and the backward
+    finds each entry's blocks with the geometric test instead: same gradients
+    (to the oracle bar)."""
+    wl = synth.workload_grad(1.0)
+    scene, cam, cfg = wl.scene, wl.cameras[0], wl.config
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    ref_f = O.render(scene, cam, cfg)
+    dC, dA, dD = synth.upstream(wl.upstream_seed, cam.width, cam.height, True, True)
+    keep = (ref_f["flag"] == 0)
+    dC, dA, dD = dC * keep[None], dA * keep, dD * keep
+    st.bins.blocks = None
+    out = ras.forward(st, sct, cam, sync=True)
+    assert not st.bins.blocks
+    g = G.gpu_backward(ras, st, sct, out, dC, dA, dD)
+    r = O.backward(scene, cam, cfg, dC, dA, dD)
+    print("no block masks", G.assert_grads(g, r))
+
+
 def test_forward_deterministic():
     wl = synth.workload_grad(1.0)
     outs = [G.to_np(G.gpu_forward(wl.scene, wl.cameras[0], wl.config)[3]) for _ in range(2)]
