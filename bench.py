@@ -33,11 +33,20 @@ G_REC = 48      # 2D gradient record (bytes)
 # --no-serve` (KiB per dispatch), each scaled by what the same counter reads
 # for a 512 MiB device copy (`bench.py --copy-probe`: FETCH_SIZE reads half
 # the copied bytes, WRITE_SIZE all of them).  Valid only for the kernel
-# source the counters were taken on: `src` is the SHA-256 of that file.
+# source the counters were taken on: `src` is the SHA-256 of its files.
 TRAFFIC = {
-    "project_bwd": {"file": "paper_2505_19175_amd/csrc/project.hip",
-                    "src": None, "fetch_kib": 2.612e5, "write_kib": 7.949e5,
+    "project_bwd": {"files": ["paper_2505_19175_amd/csrc/backproject.hip",
+                              "paper_2505_19175_amd/csrc/geometry.h",
+                              "paper_2505_19175_amd/csrc/ts_device.h"],
+                    "src": "3426376331313e629ea5383194261babc61f7b809c59e0106dbf1e7e3664f3d4",
+                    "fetch_kib": 1.615e5, "write_kib": 7.807e5,
                     "fetch_scale": 2.0, "write_scale": 1.0},
+    "project": {"files": ["paper_2505_19175_amd/csrc/project.hip",
+                          "paper_2505_19175_amd/csrc/geometry.h",
+                          "paper_2505_19175_amd/csrc/ts_device.h"],
+                "src": "8900049176f58d32fe6851a145d1e1cb683809b13b89a2fb857488ada26c8b42",
+                "fetch_kib": 2.148e5, "write_kib": 3.101e5,
+                "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
@@ -45,14 +54,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _sha(path):
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def _sha(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_bytes(kernel):
     t = TRAFFIC.get(kernel)
-    if t is None or t["src"] is None or _sha(t["file"]) != t["src"]:
+    if t is None or t["src"] is None or _sha(t["files"]) != t["src"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 

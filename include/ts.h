@@ -65,6 +65,7 @@ extern "C" {
 
 #define TS_TILE 16               /* tile edge in pixels */
 #define TS_G2D_STRIDE 16         /* floats per triangle in ts_proj.g2d */
+#define TS_CGRAD_STRIDE 12       /* floats per triangle in ts_proj.cgrad */
 #define TS_MAX_SH_DEGREE 3
 #define TS_MAX_IMAGE_DIM 16384   /* width and height limit (int16 pixel rects) */
 
@@ -94,9 +95,15 @@ typedef struct ts_proj {
     int16_t* rect;      /* [N][4] tight pixel box px0, px1, py0, py1 (px0 > px1: empty) */
     float* depth;       /* [N] depth key */
     uint32_t* ntiles;   /* [N] tiles covered; 0 = culled */
-    float* g2d;         /* [N][TS_G2D_STRIDE] per-triangle 2D gradient accumulators;
-                           zeroed by ts_project for visible triangles, consumed (and
-                           re-zeroed) by ts_render_backward */
+    float* g2d;         /* [N][TS_G2D_STRIDE] per-triangle 2D gradient accumulators:
+                           the caller zero-fills it once; every ts_render_backward (or
+                           ts_raster_backward followed by ts_project_backward) adds
+                           into it, consumes it and leaves it zero again */
+    float* cgrad;       /* [N][TS_CGRAD_STRIDE] per visible triangle, written by ts_project
+                           for the backward: J[c][b] = d(sum_k sh_kc Y_k)/d dir_b at the
+                           view direction (9 floats), then the channels whose colour is
+                           not clamped at zero (bits 0-2 of the 10th float's bits);
+                           16-byte aligned; may be NULL for forward-only use */
 } ts_proj;
 
 /* Tile lists of one view.  keys/vals/ranges are outputs of ts_bin_sort. */
@@ -193,9 +200,10 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
 /*
  * The two halves of ts_render_backward, for callers that schedule them
  * separately.  ts_raster_backward accumulates the per-triangle 2D gradients
- * into proj->g2d (which must hold zeros for visible triangles, as
- * ts_project and ts_project_backward leave it); ts_project_backward turns
- * them into gv, go, gsigma, gsh and re-zeroes proj->g2d.
+ * into proj->g2d (which must hold zeros, as the caller's zero fill and
+ * every ts_project_backward leave it); ts_project_backward turns them into
+ * gv, go, gsigma, gsh and re-zeroes the rows it consumed: call it after
+ * every ts_raster_backward.
  */
 int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
                        const ts_config* cfg, const float* dL_drgb, const float* dL_dalpha,

@@ -21,6 +21,7 @@ TS_EWORKSPACE = 3
 TS_EHIP = 4
 TS_TILE = 16
 TS_G2D_STRIDE = 16
+TS_CGRAD_STRIDE = 12
 
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
            "ts_bin_sort", "ts_render_forward", "ts_render_backward", "ts_raster_backward",
@@ -48,7 +49,8 @@ class ts_config(ctypes.Structure):
 
 class ts_proj(ctypes.Structure):
     _fields_ = [("rec", ctypes.c_void_p), ("rect", ctypes.c_void_p), ("depth", ctypes.c_void_p),
-                ("ntiles", ctypes.c_void_p), ("g2d", ctypes.c_void_p)]
+                ("ntiles", ctypes.c_void_p), ("g2d", ctypes.c_void_p),
+                ("cgrad", ctypes.c_void_p)]
 
 
 class ts_bins(ctypes.Structure):

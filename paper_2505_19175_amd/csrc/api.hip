@@ -63,7 +63,8 @@ bool proj_ok(const ts_proj* p)
     return p && p->rec && p->rect && p->depth && p->ntiles && p->g2d &&
            (reinterpret_cast<uintptr_t>(p->rec) & 15u) == 0 &&
            (reinterpret_cast<uintptr_t>(p->rect) & 7u) == 0 &&
-           (reinterpret_cast<uintptr_t>(p->g2d) & 15u) == 0;
+           (reinterpret_cast<uintptr_t>(p->g2d) & 15u) == 0 &&
+           (reinterpret_cast<uintptr_t>(p->cgrad) & 15u) == 0;
 }
 
 bool bins_ok(const ts_bins* b)
@@ -101,7 +102,7 @@ int ts_project(const float* v, const float* o, const float* sigma, const float* 
     if (!v || !o || !sigma || !sh || !proj_ok(out))
         return fail(TS_EINVAL, "ts_project: null or misaligned pointer");
     ts::launch_project(v, o, sigma, sh, N, to_cam(cam), to_cfg(cfg), out->rec, out->rect,
-                       out->depth, out->ntiles, out->g2d, stream);
+                       out->depth, out->ntiles, out->cgrad, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project");
 }
@@ -172,7 +173,7 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
     if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_render_backward: bad camera");
     if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_backward: bad config");
     if (!bins_ok(bins)) return fail(TS_EINVAL, "ts_render_backward: bad bins");
-    if (N > 0 && (!proj_ok(proj) || !v || !sh || !gv || !go || !gsigma || !gsh))
+    if (N > 0 && (!proj_ok(proj) || !proj->cgrad || !v || !sh || !gv || !go || !gsigma || !gsh))
         return fail(TS_EINVAL, "ts_render_backward: null pointer");
     if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_render_backward: null upstream");
     if (N == 0) return TS_OK;
@@ -182,7 +183,7 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
                                tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), dL_drgb,
                                dL_dalpha, dL_ddepth, T_final, last, bins->blocks, proj->g2d,
                                stream);
-    ts::launch_backproject(v, sh, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go, gsigma,
+    ts::launch_backproject(v, proj->cgrad, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go, gsigma,
                            gsh, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_backward");
@@ -215,9 +216,9 @@ int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_pro
     if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_project_backward: bad camera");
     if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_project_backward: bad config");
     if (N == 0) return TS_OK;
-    if (!proj_ok(proj) || !v || !sh || !gv || !go || !gsigma || !gsh)
+    if (!proj_ok(proj) || !proj->cgrad || !v || !sh || !gv || !go || !gsigma || !gsh)
         return fail(TS_EINVAL, "ts_project_backward: null pointer");
-    ts::launch_backproject(v, sh, N, to_cam(cam), to_cfg(cfg), proj->rect, proj->ntiles,
+    ts::launch_backproject(v, proj->cgrad, N, to_cam(cam), to_cfg(cfg), proj->rect, proj->ntiles,
                            proj->g2d, gv, go, gsigma, gsh, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project_backward");

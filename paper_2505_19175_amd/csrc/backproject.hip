@@ -1,0 +1,218 @@
+// backproject.hip -- the chain from the per-triangle 2D gradients to the
+// triangle parameters (backward).  One thread per triangle; geometry in FP64.
+#include "geometry.h"
+#include "ts_kernels.h"
+
+namespace ts {
+
+// Stores n floats of LDS to contiguous global memory, one 16-byte vector per
+// lane where the block is full (n % 4 == 0 and 16-byte aligned).
+__device__ __forceinline__ void block_store(float* __restrict__ dst, const float* src, int n)
+{
+    if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
+        float4* d4 = reinterpret_cast<float4*>(dst);
+        for (int f = threadIdx.x; f < n / 4; f += blockDim.x)
+            d4[f] = make_float4(src[4 * f], src[4 * f + 1], src[4 * f + 2], src[4 * f + 3]);
+    } else {
+        for (int f = threadIdx.x; f < n; f += blockDim.x) dst[f] = src[f];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: 2D accumulators -> window coefficients -> projected vertices ->
+// camera space -> world vertices; colour -> SH coefficients and view
+// direction.  Consumes g2d (re-zeroes it).
+// g2d slots: 0-2 dL/dA_k, 3-5 dL/dB_k, 6-8 dL/dC_k, 9 dL/do, 10 dL/dsigma,
+//            11-13 dL/drgb, 14 dL/dz.
+// A block handles 256 consecutive triangles and writes their gradient rows
+// through LDS, so every store of the block is contiguous (the SH gradient is
+// the largest array the step writes: 12 (deg+1)^2 bytes per triangle).
+// ---------------------------------------------------------------------------
+template <int DEG>
+__global__ __launch_bounds__(256) void k_backproject(
+    const float* __restrict__ v, const float4* __restrict__ cgrad, int64_t N, Cam cam, Cfg cfg,
+    const short4* __restrict__ rect, const uint32_t* __restrict__ ntiles,
+    float4* __restrict__ g2d, float* __restrict__ gv, float* __restrict__ go,
+    float* __restrict__ gsig, float* __restrict__ gsh)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int NSH = 3 * K;
+    __shared__ float s_gv[256 * 9];
+    __shared__ float s_y[256 * K];     // SH basis at the view direction
+    __shared__ float s_g[256 * 3];     // dL/drgb where the colour is not clamped
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * 256;
+    const int64_t i = base + tid;
+    const int nt = (int)min((int64_t)256, N - base);
+
+    float gvo[9], yo[K], go3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gvo[a] = 0.f;
+#pragma unroll
+    for (int a = 0; a < K; ++a) yo[a] = 0.f;
+    float go_ = 0.f, gs_ = 0.f;
+
+    if (i < N && ntiles[i] != 0u) {
+        float G[16];
+        {
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 t = g2d[4 * i + j];
+                G[4 * j + 0] = t.x; G[4 * j + 1] = t.y; G[4 * j + 2] = t.z; G[4 * j + 3] = t.w;
+                g2d[4 * i + j] = z4;
+            }
+        }
+        go_ = G[9];
+        gs_ = G[10];
+
+        float vv[9];
+        load_vertices(v, i, vv);
+        Geo g;
+        project_geo(vv, cam, cfg.z_near, g);
+        const short4 rc = rect[i];
+        const double ax = (double)rc.x, ay = (double)rc.z;
+
+        // coefficients -> (w_k, e_k, q_k)
+        double gq[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        double ge[3][2];
+        double gP = 0.0, gS = 0.0, gl[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double w = g.P / (g.S * g.len[k]);
+            const double qx = g.q[k][0] - ax, qy = g.q[k][1] - ay;
+            const double ex = g.e[k][0], ey = g.e[k][1];
+            const double gA = G[k], gB = G[3 + k], gC = G[6 + k];
+            const double ck = ex * (0.5 - qy) - ey * (0.5 - qx);
+            const double gw = -gA * ey + gB * ex + gC * ck;
+            ge[k][0] = gB * w + gC * w * (0.5 - qy);
+            ge[k][1] = -gA * w - gC * w * (0.5 - qx);
+            gq[k][0] += gC * w * ey;
+            gq[k][1] += -gC * w * ex;
+            // w = P / (S l_k)
+            gP += gw / (g.S * g.len[k]);
+            gS += -gw * w / g.S;
+            gl[k] = -gw * w / g.len[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double gl_k = gl[k] + gP;               // P = sum l_k
+            ge[k][0] += gl_k * g.e[k][0] / g.len[k];      // l_k = |e_k|
+            ge[k][1] += gl_k * g.e[k][1] / g.len[k];
+        }
+        // S = x0 (y1 - y2) + x1 (y2 - y0) + x2 (y0 - y1)
+        gq[0][0] += gS * (g.q[1][1] - g.q[2][1]);
+        gq[0][1] += gS * (g.q[2][0] - g.q[1][0]);
+        gq[1][0] += gS * (g.q[2][1] - g.q[0][1]);
+        gq[1][1] += gS * (g.q[0][0] - g.q[2][0]);
+        gq[2][0] += gS * (g.q[0][1] - g.q[1][1]);
+        gq[2][1] += gS * (g.q[1][0] - g.q[0][0]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {                     // e_k = q_{k+1} - q_k
+            const int k1 = k == 2 ? 0 : k + 1;
+            gq[k1][0] += ge[k][0]; gq[k1][1] += ge[k][1];
+            gq[k][0] -= ge[k][0];  gq[k][1] -= ge[k][1];
+        }
+
+        // projection q = (fx x/z + cx, fy y/z + cy); depth key = mean z
+        const double gz3 = (double)G[14] * (1.0 / 3.0);
+        double gw_[3][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double x = g.xc[j][0], y = g.xc[j][1], z = g.xc[j][2];
+            const double iz = 1.0 / z;
+            const double gx0 = cam.fx * iz * gq[j][0];
+            const double gx1 = cam.fy * iz * gq[j][1];
+            const double gx2 = -(cam.fx * x * gq[j][0] + cam.fy * y * gq[j][1]) * iz * iz + gz3;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)                   // R^T gx
+                gw_[j][b] = (double)cam.R[b] * gx0 + (double)cam.R[3 + b] * gx1 +
+                            (double)cam.R[6 + b] * gx2;
+        }
+
+        // colour: rgb = max(0, sum_k sh_k Y_k(d) + 1/2).  The projection kept
+        // the unclamped channels and J[c][b] = sum_k sh_kc dY_k/d dir_b.
+        double d[3], nrm;
+        view_dir(vv, cam, d, nrm);
+        float Y[16];
+        sh_basis(DEG, (float)d[0], (float)d[1], (float)d[2], Y);
+        const float4 c0 = cgrad[3 * i], c1 = cgrad[3 * i + 1], c2 = cgrad[3 * i + 2];
+        const uint32_t open = __float_as_uint(c2.y);
+        const float gr0 = (open & 1u) ? G[11] : 0.f;
+        const float gr1 = (open & 2u) ? G[12] : 0.f;
+        const float gr2 = (open & 4u) ? G[13] : 0.f;
+        go3[0] = gr0; go3[1] = gr1; go3[2] = gr2;
+#pragma unroll
+        for (int k = 0; k < K; ++k) yo[k] = Y[k];
+        float gd[3];
+        gd[0] = gr0 * c0.x + gr1 * c0.w + gr2 * c1.z;
+        gd[1] = gr0 * c0.y + gr1 * c1.x + gr2 * c1.w;
+        gd[2] = gr0 * c0.z + gr1 * c1.y + gr2 * c2.x;
+        // d = dv/|dv|, dv = centroid - camera centre, centroid = mean of vertices
+        const double dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double gdv = ((double)gd[b] - d[b] * dd) / nrm * (1.0 / 3.0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gw_[j][b] += gdv;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) gvo[3 * j + b] = (float)gw_[j][b];
+    }
+    if (i < N) {
+        go[i] = go_;
+        gsig[i] = gs_;
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) s_gv[tid * 9 + a] = gvo[a];
+#pragma unroll
+    for (int a = 0; a < K; ++a) s_y[tid * K + a] = yo[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s_g[tid * 3 + a] = go3[a];
+    __syncthreads();
+    block_store(gv + base * 9, s_gv, nt * 9);
+    // dL/dsh[t][k][c] = Y_k(d_t) dL/drgb_c, written as contiguous rows
+    float* dst = gsh + base * NSH;
+    const int n = nt * NSH;
+    if constexpr (NSH % 4 == 0) {
+        constexpr int R4 = NSH / 4;   // float4 per row
+        float4* d4 = reinterpret_cast<float4*>(dst);
+        if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0) {
+            for (int f = tid; f < n / 4; f += 256) {
+                const int t = f / R4, q0 = 4 * (f - t * R4);
+                float x[4];
+#pragma unroll
+                for (int cq = 0; cq < 4; ++cq) {
+                    const int q = q0 + cq, k = q / 3, ch = q - 3 * k;
+                    x[cq] = s_y[t * K + k] * s_g[t * 3 + ch];
+                }
+                d4[f] = make_float4(x[0], x[1], x[2], x[3]);
+            }
+            return;
+        }
+    }
+    for (int f = tid; f < n; f += 256) {
+        const int t = f / NSH, q = f - t * NSH, k = q / 3, ch = q - 3 * k;
+        dst[f] = s_y[t * K + k] * s_g[t * 3 + ch];
+    }
+}
+
+void launch_backproject(const float* v, const float* cgrad, int64_t N, const Cam& cam,
+                        const Cfg& cfg, const int16_t* rect, const uint32_t* ntiles, float* g2d,
+                        float* gv, float* go, float* gsig, float* gsh, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    const short4* r4 = reinterpret_cast<const short4*>(rect);
+    float4* g4 = reinterpret_cast<float4*>(g2d);
+    const float4* cg = reinterpret_cast<const float4*>(cgrad);
+    switch (cfg.deg) {
+    case 0: hipLaunchKernelGGL(k_backproject<0>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
+    case 1: hipLaunchKernelGGL(k_backproject<1>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
+    case 2: hipLaunchKernelGGL(k_backproject<2>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
+    default: hipLaunchKernelGGL(k_backproject<3>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
+    }
+}
+
+}  // namespace ts

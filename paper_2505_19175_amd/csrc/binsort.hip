@@ -10,9 +10,9 @@
 //      ceil(log2 tiles / 8) passes over M; inside a tile the triangles are
 //      still in index order
 //   4. one workgroup per tile sorts that tile's entries by depth key with a
-//      stable block radix sort (in registers and LDS up to 2048 entries, in
-//      two global ping-pong buffers beyond), skipping the 8-bit digits that
-//      are equal over the whole tile
+//      stable radix sort (one wave in registers up to 1024 entries, four
+//      waves and a merge up to 4096, two global ping-pong buffers beyond),
+//      skipping the 8-bit digits that are equal over the whole tile
 // A stable sort by depth of a list in index order is the (depth, index)
 // order, so the result is exactly the (tile, depth, index) order.  Nothing is
 // gathered in a random order except the depth key of each instance.
@@ -169,6 +169,10 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
 // ---------------------------------------------------------------------------
 // 2. instances in index order
 // ---------------------------------------------------------------------------
+// The block's instances fill one contiguous range of the list, written slot
+// by slot by consecutive lanes (coalesced): slot q finds its entry by a
+// binary search over the per-thread prefix counts, then a walk over that
+// thread's kItems entries, and its tile from the entry's tile rectangle.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntiles,
                                               const short4* __restrict__ rect, int64_t N_host,
                                               const uint32_t* __restrict__ d_n,
@@ -178,25 +182,39 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
                                               uint32_t* __restrict__ tv)
 {
     __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_pre[kBlock];         // instances before each thread's entries
+    __shared__ uint32_t s_cnt[kChunk];         // tiles of every entry of the block
     const int64_t N = d_n ? (int64_t)*d_n : N_host;
     if ((int64_t)blockIdx.x >= nblocks(N)) return;
-    const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
-    uint32_t cnt[kItems], c = 0;
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    uint32_t c = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r;
-        cnt[r] = i < N ? ntiles[i] : 0u;
-        c += cnt[r];
+        const int64_t i = base + tid * kItems + r;
+        const uint32_t n = i < N ? ntiles[i] : 0u;
+        s_cnt[tid * kItems + r] = n;
+        c += n;
     }
     uint32_t tot;
-    uint64_t pos = block_exclusive_scan(c, tot, s_tmp) + (uint64_t)blk[blockIdx.x];
+    s_pre[tid] = block_exclusive_scan(c, tot, s_tmp);
+    __syncthreads();
+    const uint64_t out0 = (uint64_t)blk[blockIdx.x];
+    for (uint32_t q = tid; q < tot; q += kBlock) {
+        if (out0 + q >= capacity) break;
+        int t = 0;   // last thread whose first instance is at or before q
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        if (cnt[r] == 0u) continue;
-        const uint32_t e = (uint32_t)(base + r);
+        for (int step = kBlock / 2; step > 0; step >>= 1)
+            if (s_pre[t + step] <= q) t += step;
+        uint32_t k = q - s_pre[t];
+        int r = 0;
+        while (k >= s_cnt[t * kItems + r]) {   // ends within the thread's entries
+            k -= s_cnt[t * kItems + r];
+            ++r;
+        }
+        const uint32_t e = (uint32_t)(base + t * kItems + r);
         const short4 rc = rect[e];
-        const int tx0 = rc.x / kTile, tx1 = rc.y / kTile;
-        const int ty0 = rc.z / kTile, ty1 = rc.w / kTile;
+        const int tx0 = rc.x / kTile, nx = rc.y / kTile - tx0 + 1, ty0 = rc.z / kTile;
         uint32_t toff = 0;
         int tw = tiles_x;
         if (views) {   // batched: entry = view * per_view + triangle
@@ -204,14 +222,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
             toff = V.tile_offset;
             tw = (int)V.tiles_x;
         }
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                if (pos < capacity) {
-                    tk[pos] = toff + (uint32_t)(ty * tw + tx);
-                    tv[pos] = e;
-                }
-                ++pos;
-            }
+        const int dy = (int)(k / (uint32_t)nx), dx = (int)(k - (uint32_t)(dy * nx));
+        tk[out0 + q] = toff + (uint32_t)((ty0 + dy) * tw + tx0 + dx);
+        tv[out0 + q] = e;
     }
 }
 
@@ -515,70 +528,7 @@ __device__ uint32_t varying_bits(uint32_t a, uint32_t o, SortSmem& s)
     return diff;
 }
 
-// L <= kChunk: keys in registers, exchanged through LDS after every pass.
-__device__ void sort_tile_small(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
-                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
-                                SortSmem& sm)
-{
-    const int tid = threadIdx.x, w = tid >> 6;
-    uint32_t key[kItems], val[kItems], rank[kItems];
-    uint32_t a = ~0u, o = 0u;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int j = r * kBlock + tid;
-        key[r] = 0u;
-        val[r] = 0u;
-        rank[r] = 0u;
-        if (j < L) {
-            val[r] = vals[s0 + j];
-            key[r] = __float_as_uint(depth[val[r]]);   // positive floats order as unsigned ints
-            a &= key[r];
-            o |= key[r];
-        }
-    }
-    const uint32_t diff = varying_bits(a, o, sm);
-    bool moved = false;
-    for (int p = 0; p < 4; ++p) {
-        const int shift = 8 * p;
-        if (((diff >> shift) & 0xffu) == 0u) continue;   // one digit value: order unchanged
-        moved = true;
-        const uint32_t cnt = rank_chunk(key, L, shift, sm, rank);
-        uint32_t tot;
-        const uint32_t pre = block_exclusive_scan(cnt, tot, sm.tmp);
-        sm.base[tid] = pre;
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            const int j = r * kBlock + tid;
-            if (j < L) {
-                const uint32_t d = (key[r] >> shift) & 0xffu;
-                const uint32_t pos = sm.base[d] + sm.cnt[r * 4 + w][d] + rank[r];
-                sm.key[pos] = key[r];
-                sm.val[pos] = val[r];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kItems; ++r) {
-            const int j = r * kBlock + tid;
-            if (j < L) {
-                key[r] = sm.key[j];
-                val[r] = sm.val[j];
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int j = r * kBlock + tid;
-        if (j < L) {
-            if (moved) vals[s0 + j] = val[r];
-            if (keys) keys[s0 + j] = tile_key(t, key[r]);
-        }
-    }
-}
-
-// L > kChunk: each pass histograms the whole tile, then scatters it chunk by
+// L > 4 kWaveMax: each pass histograms the whole tile, then scatters it chunk by
 // chunk in order between two global buffers (k1/v1, k0/v0 at the tile's own
 // offsets); the last pass writes vals.  A single pass goes through k1/v1 and
 // is copied back, so no pass reads and writes the same buffer.
@@ -696,7 +646,7 @@ __device__ __forceinline__ void wave_sync()
 // plus its rank in the group.
 __device__ void sort_tile_wave(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
-                               WaveSmem& sm)
+                               WaveSmem& sm, bool to_lds)
 {
     const int lane = threadIdx.x & 63;
     const int R = (L + 63) >> 6;
@@ -799,6 +749,19 @@ __device__ void sort_tile_wave(int L, uint32_t s0, uint32_t t, const float* __re
         }
         wave_sync();
     }
+    if (to_lds) {   // leave the sorted run in sm.key / sm.val for a merge
+        if (!moved) {
+#pragma unroll
+            for (int r = 0; r < kWaveItems; ++r) {
+                const int j = r * 64 + lane;
+                if (j < L) {
+                    sm.key[j] = key[r];
+                    sm.val[j] = val[r];
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < kWaveItems; ++r) {
         const int j = r * 64 + lane;
@@ -809,10 +772,48 @@ __device__ void sort_tile_wave(int L, uint32_t s0, uint32_t t, const float* __re
     }
 }
 
+// First index of sorted a[0, n) whose key is above x (upper = true) or at
+// least x (upper = false).
+__device__ __forceinline__ int bound(const uint32_t* a, int n, uint32_t x, bool upper)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint32_t v = a[mid];
+        if (upper ? v <= x : v < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Stable 4-way merge of a run of L entries whose four quarters (contiguous
+// index ranges of length Q, the last one shorter) each wave has sorted into
+// its LDS buffer: every entry goes to its own rank plus, per other quarter,
+// the number of that quarter's entries preceding it -- keys below, and equal
+// keys of earlier quarters -- found by binary search.  The result is the
+// (depth, index) order.
+__device__ void merge_quarters(int L, int Q, uint32_t s0, uint32_t t,
+                               uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
+                               const WaveSmem (&wv)[kBlock / 64])
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    auto qlen = [&](int q) { return max(0, min(Q, L - q * Q)); };
+    const int mine = qlen(w);
+    for (int j = lane; j < mine; j += 64) {
+        const uint32_t k = wv[w].key[j];
+        int pos = j;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q != w) pos += bound(wv[q].key, qlen(q), k, q < w);
+        vals[s0 + pos] = wv[w].val[j];
+        if (keys) keys[s0 + pos] = tile_key(t, k);
+    }
+}
+
 // Tiles taken in `order` (longest first); the first n_long of them are longer
-// than kWaveMax and get a whole workgroup each (registers + LDS up to kChunk
-// entries, global ping-pong beyond); every later workgroup gives each of its
-// four waves one tile.  The instances of a tile arrive in index order; they
+// than kWaveMax and get a whole workgroup each (four wave-level sorts of a
+// quarter each and a merge up to 4 kWaveMax entries, global ping-pong beyond);
+// every later workgroup gives each of its four waves one tile.  The instances of a tile arrive in index order; they
 // leave in (depth, index) order, with their 64-bit keys when keys is set.
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order,
@@ -841,16 +842,25 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     if (t >= (uint32_t)num_tiles) return;
     const uint32_t s0 = ranges[2 * t];
     const int64_t L = (int64_t)ranges[2 * t + 1] - (int64_t)s0;
-    if (blockIdx.x < nl) {   // the whole workgroup
-        if (L <= kChunk)
-            sort_tile_small((int)L, s0, t, depth, vals, keys, sm.blk);
-        else
-            sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
-    } else if (L == 1) {
+    const int w = threadIdx.x >> 6;
+    if (blockIdx.x < nl && L > 4 * kWaveMax) {   // the whole workgroup, in global memory
+        sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
+        return;
+    }
+    // one wave-level sort per wave: a whole tile, or a quarter of a long one
+    const bool split = blockIdx.x < nl;          // the same for the whole workgroup
+    const int Q = (int)((L + 3) >> 2);
+    const int wl = split ? max(0, min(Q, (int)L - w * Q)) : (int)L;
+    const uint32_t ws0 = split ? s0 + (uint32_t)(w * Q) : s0;
+    if (!split && wl == 1) {
         if (keys && (threadIdx.x & 63) == 0)
             keys[s0] = tile_key(t, __float_as_uint(depth[vals[s0]]));
-    } else if (L > 1 && L <= kWaveMax) {
-        sort_tile_wave((int)L, s0, t, depth, vals, keys, sm.wave[threadIdx.x >> 6]);
+    } else if (wl > 0 && wl <= kWaveMax) {
+        sort_tile_wave(wl, ws0, t, depth, vals, keys, sm.wave[w], split);
+    }
+    if (split) {
+        __syncthreads();   // every quarter sorted, and all reads of vals done
+        merge_quarters((int)L, Q, s0, t, vals, keys, sm.wave);
     }
 }
 

@@ -48,13 +48,28 @@ union RecView {
 // tests are the separating axes of the tight region (a triangle) and the
 // block's square of pixel centres.  The slack covers the rounding of this
 // evaluation and of the per-pixel one, so no pixel that composites is lost.
+//
+// The staged copy holds C_k relative to the tile's corner pixel (tx0, ty0)
+// instead of the record's anchor, so a lane evaluates u_k = A_k dx + B_k dy +
+// C_k with its own fixed offset in the tile (no per-step conversion).
+__device__ __forceinline__ void write_stage(Stage& S, RecView& u, int tx0, int ty0)
+{
+    const double ox = (double)(tx0 - u.r.ax), oy = (double)(ty0 - u.r.ay);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u.r.C[k] = fma(u.r.A[k], ox, fma(u.r.B[k], oy, u.r.C[k]));
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = u.q[c];
+    S.z[threadIdx.x] = u.r.z;
+}
+
 __device__ __forceinline__ void stage_copy(Stage& S, const TriRecord* __restrict__ rec,
-                                           uint32_t tri)
+                                           uint32_t tri, int tx0, int ty0)
 {
     const float4* src = reinterpret_cast<const float4*>(rec + tri);
+    RecView u;
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = src[c];
-    S.z[threadIdx.x] = rec[tri].z;
+    for (int c = 0; c < 7; ++c) u.q[c] = src[c];
+    write_stage(S, u, tx0, ty0);
 }
 
 __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restrict__ rec,
@@ -64,9 +79,7 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
     RecView u;
 #pragma unroll
     for (int c = 0; c < 8; ++c) u.q[c] = src[c];
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = u.q[c];
-    S.z[threadIdx.x] = u.r.z;
+    write_stage(S, u, tx0, ty0);
     uint32_t cx = 0, cy = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -78,10 +91,9 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
 #pragma unroll
     for (int by = 0; by < 4; ++by) box |= ((cy >> by) & 1u) ? (cx << (4 * by)) : 0u;
 
-    const double dx0 = (double)(tx0 - u.r.ax), dy0 = (double)(ty0 - u.r.ay);
     const double ut = (double)u.r.ut;
-    // coefficients read back from this thread's own LDS slot, one edge at a
-    // time, to keep the register peak of the staging step low
+    // tile-relative coefficients read back from this thread's own LDS slot,
+    // one edge at a time, to keep the register peak of the staging step low
     const double* cf = reinterpret_cast<const double*>(&S.q[0][0]);
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
@@ -89,10 +101,9 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
             return cf[2 * (size_t)((idx >> 1) * kBatch + threadIdx.x) + (idx & 1)];
         };
         const double A = coef(k), B = coef(3 + k), C = coef(6 + k);
-        const double cxk = dx0 + (A > 0.0 ? 3.0 : 0.0), cyk = dy0 + (B > 0.0 ? 3.0 : 0.0);
+        const double cxk = A > 0.0 ? 3.0 : 0.0, cyk = B > 0.0 ? 3.0 : 0.0;
         const double base = fma(A, cxk, fma(B, cyk, C));   // largest u_k over block (0, 0)
-        const double slack = 0x1p-46 * (fabs(C) + fabs(A) * (fabs(dx0) + 16.0) +
-                                        fabs(B) * (fabs(dy0) + 16.0));
+        const double slack = 0x1p-46 * (fabs(C) + 16.0 * (fabs(A) + fabs(B)));
         const double lim = ut - slack;
         const double A4 = 4.0 * A, B4 = 4.0 * B;
 #pragma unroll 1
@@ -169,13 +180,14 @@ __device__ __forceinline__ int per_row(int g, int j0, int j1, int j2, int j3)
     return g == 0 ? j0 : g == 1 ? j1 : g == 2 ? j2 : j3;
 }
 
-// Window and opacity of a record at pixel offset (dx, dy); u <= 0 gives
-// alpha = 0.  Forward and backward call exactly this.
-__device__ __forceinline__ double frag_alpha(const TriRecord& r, int dx, int dy,
+// Window and opacity of a staged record at the pixel (dx, dy) from the
+// tile's corner; u <= 0 gives alpha = 0.  Forward and backward call exactly
+// this.
+__device__ __forceinline__ double frag_alpha(const TriRecord& r, double dx, double dy,
                                              float alpha_max, Frag& f)
 {
     int k;
-    const double u = edge_min(r.A, r.B, r.C, (double)dx, (double)dy, k);
+    const double u = edge_min(r.A, r.B, r.C, dx, dy, k);
     window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
     f.k = k;
     return u;
@@ -228,6 +240,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     bool done = !inside;
 
     const uint32_t my_bit = 1u << (4 * P.w + P.g);
+    const double dxt = (double)(P.px - J.tx * kTile), dyt = (double)(P.py - J.ty * kTile);
     for (uint32_t b = start; b < end; b += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b);
         __syncthreads();
@@ -251,7 +264,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             jn = lst[k + 1 < kBatch ? k + 1 : 0];
             const TriRecord r = read_rec(S, j);
             Frag f;
-            const double u = frag_alpha(r, P.px - r.ax, P.py - r.ay, cfg.alpha_max, f);
+            const double u = frag_alpha(r, dxt, dyt, cfg.alpha_max, f);
             const bool contrib = act && u > 0.0 && f.a >= cfg.alpha_min;
             const float Tn = T * (1.f - f.a);
             const bool stop = contrib && Tn < cfg.T_min;
@@ -417,6 +430,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
 
     const int64_t p = (int64_t)P.py * cam.W + P.px;
     const int64_t hw = (int64_t)cam.W * cam.H;
+    const double dxt = (double)(P.px - tx * kTile), dyt = (double)(P.py - ty * kTile);
     float T = 1.f, Tf = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gA = 0.f, gD = 0.f;
     uint32_t my_last = 0;
     if (inside) {
@@ -454,7 +468,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             const uint32_t tri = vals[start + lo_ + tid];
             s_tri[tid] = tri;
             if (blocks) {   // the forward's record of where the entry composited
-                stage_copy(S, rec, tri);
+                stage_copy(S, rec, tri, tx * kTile, ty * kTile);
                 S.hit[tid] = blocks[start + lo_ + tid];
             } else {
                 S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, tx * kTile, ty * kTile);
@@ -476,9 +490,9 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             jn = lst[kn >= 0 ? kn : 0];
             const int j = k >= 0 ? jc : -1;
             const TriRecord r = read_rec(S, jc);
-            const int dx = P.px - r.ax, dy = P.py - r.ay;
+            const int dx = P.px - r.ax, dy = P.py - r.ay;   // anchor form of the coefficients
             Frag f;
-            const double u = frag_alpha(r, dx, dy, cfg.alpha_max, f);
+            const double u = frag_alpha(r, dxt, dyt, cfg.alpha_max, f);
             const bool contrib = j >= 0 && inside && lo_ + (uint32_t)j < my_last && u > 0.0 &&
                                  f.a >= cfg.alpha_min;
             if (__ballot(contrib) == 0ull) continue;

@@ -13,7 +13,7 @@ struct Cfg;
 
 void launch_project(const float* v, const float* o, const float* sigma, const float* sh,
                     int64_t N, const Cam& cam, const Cfg& cfg, void* rec, int16_t* rect,
-                    float* depth, uint32_t* ntiles, float* g2d, hipStream_t stream);
+                    float* depth, uint32_t* ntiles, float* cgrad, hipStream_t stream);
 
 void launch_project_views(const float* v, const float* o, const float* sigma, const float* sh,
                           int64_t N, const ts_view* views, const uint32_t* ctl, const Cfg& cfg,
@@ -25,7 +25,7 @@ void launch_project_views(const float* v, const float* o, const float* sigma, co
 void launch_batch_ctl(const uint32_t* ctl_in, uint32_t max_views, uint32_t max_tiles,
                       int64_t per_view, uint32_t* ctl_out, hipStream_t stream);
 
-void launch_backproject(const float* v, const float* sh, int64_t N, const Cam& cam,
+void launch_backproject(const float* v, const float* cgrad, int64_t N, const Cam& cam,
                         const Cfg& cfg, const int16_t* rect, const uint32_t* ntiles, float* g2d,
                         float* gv, float* go, float* gsig, float* gsh, hipStream_t stream);
 

@@ -44,14 +44,17 @@ class ViewState:
         self.rect = torch.empty((n, 4), dtype=torch.int16, device=dev)
         self.depth_key = torch.empty(n, dtype=torch.float32, device=dev)
         self.ntiles = torch.empty(n, dtype=torch.int32, device=dev)
-        self.g2d = torch.empty((n, B.TS_G2D_STRIDE), dtype=torch.float32, device=dev)
+        # zero once; every backward consumes its accumulations and clears them
+        self.g2d = torch.zeros((n, B.TS_G2D_STRIDE), dtype=torch.float32, device=dev)
+        self.cgrad = torch.empty((n, B.TS_CGRAD_STRIDE), dtype=torch.float32, device=dev)
         self.ranges = torch.empty((self.num_tiles, 2), dtype=torch.int32, device=dev)
         self.order = torch.empty(max(self.num_tiles, 1), dtype=torch.int32, device=dev)
         self.d_count = torch.zeros(4, dtype=torch.int32, device=dev)
         self.want_keys = keys
         self._alloc_lists(capacity)
         self.proj = B.ts_proj(self.rec.data_ptr(), self.rect.data_ptr(), self.depth_key.data_ptr(),
-                              self.ntiles.data_ptr(), self.g2d.data_ptr())
+                              self.ntiles.data_ptr(), self.g2d.data_ptr(),
+                              self.cgrad.data_ptr())
         self.count = (ctypes.c_uint32 * 2)()
         self.M = None
         self.N_v = None

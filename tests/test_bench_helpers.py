@@ -25,7 +25,7 @@ def test_algorithmic_bytes_formula():
 def test_traffic_is_tied_to_the_kernel_source():
     for name, t in bench.TRAFFIC.items():
         got = bench.traffic_bytes(name)
-        if t["src"] is None or bench._sha(t["file"]) != t["src"]:
+        if t["src"] is None or bench._sha(t["files"]) != t["src"]:
             assert got is None
         else:
             want = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])

@@ -198,12 +198,13 @@ def _one_tile_soup(seed, n, mode):
 
 @pytest.mark.parametrize("n,mode", [(2, "spread"), (65, "wide"), (700, "equal"), (1024, "spread"),
                                     (1024, "ulps"), (1025, "ulps"), (1500, "equal"),
-                                    (2048, "spread"), (2049, "spread"), (5000, "equal"),
-                                    (5000, "ulps"), (5000, "spread"), (4500, "wide")])
+                                    (2048, "spread"), (2049, "spread"), (4096, "spread"),
+                                    (4097, "ulps"), (5000, "equal"), (5000, "ulps"),
+                                    (5000, "spread"), (4500, "wide")])
 def test_bins_one_deep_tile(n, mode):
     """The per-tile depth sort in its three forms (one wave up to 1024
-    entries, a workgroup in registers up to 2048, global ping-pong beyond)
-    and with 0, 1, 3 and 4 digit passes; ties keep index order.  Bit-exact
+    entries, four waves and a merge up to 4096, global ping-pong beyond) and
+    with 0, 1, 3 and 4 digit passes; ties keep index order.  Bit-exact
     against the oracle's stable sort."""
     sc, cam = _one_tile_soup(61, n, mode)
     cfg = Config(sh_degree=0)
