@@ -94,13 +94,18 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t& t
 // ---------------------------------------------------------------------------
 // 1. tile counts in index order
 // ---------------------------------------------------------------------------
-// Per block of kChunk entries: the number of instances and of visible entries.
+// Per block of kChunk entries: the number of instances and of visible
+// entries.  The grid also clears the n_ranges words of the tile ranges.
 __global__ __launch_bounds__(256) void k_count(const uint32_t* __restrict__ ntiles,
                                                int64_t N_host, const uint32_t* __restrict__ d_n,
                                                uint32_t* __restrict__ blk,
-                                               uint32_t* __restrict__ blk_vis)
+                                               uint32_t* __restrict__ blk_vis,
+                                               uint32_t* __restrict__ ranges, int64_t n_ranges)
 {
     __shared__ uint32_t s_tmp[4];
+    for (int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x; f < n_ranges;
+         f += (int64_t)gridDim.x * kBlock)
+        ranges[f] = 0u;
     const int64_t N = d_n ? (int64_t)*d_n : N_host;
     if ((int64_t)blockIdx.x >= nblocks(N)) return;
     const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
@@ -394,52 +399,55 @@ constexpr int kLenBuckets = 2048;
 constexpr int kWaveMax = 1024;   // longest list one wave sorts on its own
 static_assert(kWaveMax < kLenBuckets - 1, "long tiles must lead the order");
 
-__global__ __launch_bounds__(256) void k_tile_order(const uint32_t* __restrict__ ranges,
-                                                    int n_host, const uint32_t* __restrict__ d_n,
-                                                    uint32_t* __restrict__ order,
-                                                    uint32_t* __restrict__ n_long)
+constexpr int kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(
+    const uint32_t* __restrict__ ranges, int n_host, const uint32_t* __restrict__ d_n,
+    uint32_t* __restrict__ order, uint32_t* __restrict__ n_long)
 {
     __shared__ uint32_t h[kLenBuckets];
-    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_w[kOrderThreads / 64];
     __shared__ uint32_t s_long;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int n = d_n ? (int)min(*d_n, (uint32_t)n_host) : n_host;
-    for (int b = threadIdx.x; b < kLenBuckets; b += kBlock) h[b] = 0u;
-    if (threadIdx.x == 0) s_long = 0u;
+    for (int b = tid; b < kLenBuckets; b += kOrderThreads) h[b] = 0u;
+    if (tid == 0) s_long = 0u;
     __syncthreads();
     auto len_of = [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; };
     auto key = [&](int t) {
         return (kLenBuckets - 1) - (int)min(len_of(t), (uint32_t)(kLenBuckets - 1));
     };
-    for (int t = threadIdx.x; t < n; t += kBlock) {
+    for (int t = tid; t < n; t += kOrderThreads) {
         atomicAdd(&h[key(t)], 1u);
         if (len_of(t) > (uint32_t)kWaveMax) atomicAdd(&s_long, 1u);
     }
     __syncthreads();
-    if (n_long && threadIdx.x == 0) n_long[0] = s_long;
-    constexpr int per = kLenBuckets / kBlock;
-    uint32_t loc[per], s = 0;
+    if (n_long && tid == 0) n_long[0] = s_long;
+    // exclusive scan of the bucket counts, two consecutive buckets per thread
+    static_assert(kLenBuckets == 2 * kOrderThreads, "two buckets per thread");
+    const uint32_t a0 = h[2 * tid], a1 = h[2 * tid + 1], sum = a0 + a1;
+    uint32_t inc = sum;
 #pragma unroll
-    for (int r = 0; r < per; ++r) {
-        loc[r] = h[threadIdx.x * per + r];
-        s += loc[r];
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
     }
-    uint32_t tot;
-    uint32_t pre = block_exclusive_scan(s, tot, s_tmp);
-#pragma unroll
-    for (int r = 0; r < per; ++r) {
-        h[threadIdx.x * per + r] = pre;
-        pre += loc[r];
-    }
+    if (lane == 63) s_w[w] = inc;
     __syncthreads();
-    for (int t = threadIdx.x; t < n; t += kBlock) order[atomicAdd(&h[key(t)], 1u)] = (uint32_t)t;
+    uint32_t pre = inc - sum;
+    for (int j = 0; j < w; ++j) pre += s_w[j];
+    h[2 * tid] = pre;
+    h[2 * tid + 1] = pre + a0;
+    __syncthreads();
+    for (int t = tid; t < n; t += kOrderThreads) order[atomicAdd(&h[key(t)], 1u)] = (uint32_t)t;
 }
 
 void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
                        uint32_t* order, hipStream_t stream, uint32_t* n_long)
 {
     if (order && num_tiles > 0)
-        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kBlock), 0, stream, ranges, num_tiles,
-                           d_tiles, order, n_long);
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, stream, ranges,
+                           num_tiles, d_tiles, order, n_long);
 }
 
 
@@ -912,10 +920,9 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     uint32_t* d_ovf = out.d_count + 2;  // [2] overflow
     uint32_t* d_sortn = ws.ctl;         // min(M, capacity)
 
-    launch_fill_u32(out.ranges, 2 * (int64_t)num_tiles, 0u, stream);
-    // 1. tile counts of the N (or *d_n) entries in index order
+    // 1. tile counts of the N (or *d_n) entries in index order; ranges cleared
     hipLaunchKernelGGL(k_count, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, N, d_n,
-                       ws.blk, ws.blk_vis);
+                       ws.blk, ws.blk_vis, out.ranges, 2 * (int64_t)num_tiles);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk, d_n, N, d_M,
                        d_sortn, out.capacity, d_ovf, (const uint32_t*)ws.blk_vis, d_Nv);
     int64_t m_max = (int64_t)out.capacity;
