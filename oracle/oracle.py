@@ -48,9 +48,11 @@ def _configure(L):
                                 ctypes.c_int, P, ctypes.c_int64, P, P, P, P, P, P, P, P]
     L.oracle_backward.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
                                   ctypes.c_int, P, ctypes.c_int64, P, P, P, P, P, P, P, P]
+    L.oracle_prune_stats.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
+                                     ctypes.c_int, P, ctypes.c_int64, P, P, P]
     L.oracle_threads.argtypes = []
     for f in (L.oracle_setup, L.oracle_window, L.oracle_sh, L.oracle_render,
-              L.oracle_backward, L.oracle_threads):
+              L.oracle_backward, L.oracle_prune_stats, L.oracle_threads):
         f.restype = ctypes.c_int
     return L
 
@@ -187,6 +189,23 @@ def render(scene, cam, cfg, pix: Optional[np.ndarray] = None) -> dict:
         H, W = cam.height, cam.width
         out = {k: (a.reshape(3, H, W) if k == "rgb" else a.reshape(H, W)) for k, a in out.items()}
     return out
+
+
+def prune_stats(scene, cam, cfg, pix: Optional[np.ndarray] = None) -> dict:
+    """Pruning statistics of one view (Sec. 3.2, "Pruning"): per triangle the
+    largest T*o at its composited fragments and the number of pixels where it
+    is composited, over the given pixels (default: all)."""
+    N = scene.n
+    v, o, s, sh = _scene_arrays(scene)
+    pixa = None if pix is None else np.ascontiguousarray(pix, np.int64)
+    npix = cam.width * cam.height if pixa is None else pixa.size
+    maxw = np.zeros(max(N, 1))
+    npx = np.zeros(max(N, 1), np.int32)
+    rc = lib().oracle_prune_stats(N, _p(v), _p(o), _p(s), _p(sh), _deg(scene, cfg),
+                                  _p(_cam16(cam)), cam.width, cam.height, _p(_cfg8(cfg)), npix,
+                                  _p(pixa), _p(maxw), _p(npx))
+    assert rc == 0
+    return dict(max_weight=maxw[:N], pixels=npx[:N])
 
 
 def backward(scene, cam, cfg, dC, dA=None, dD=None, pix: Optional[np.ndarray] = None) -> dict:

@@ -544,6 +544,54 @@ int oracle_render(int N, const double* v, const double* o, const double* sigma,
     return 0;
 }
 
+/* Pruning statistics (Sec. 3.2, "Pruning"): over the given pixels (all of
+ * them when pix is NULL), for every triangle the largest blending weight
+ * T * o at a fragment of it that is composited (T the transmittance in front
+ * of the fragment, o the triangle's opacity) and the number of pixels where
+ * it is composited.  maxw[N] and npix[N] are overwritten (0 where never
+ * composited). */
+int oracle_prune_stats(int N, const double* v, const double* o, const double* sigma,
+                       const double* sh, int deg, const double* cam16, int W, int H,
+                       const double* cfg8, int64_t npix, const int64_t* pix,
+                       double* maxw, int* npx)
+{
+    ocam cam; ocfg cfg; oscene S;
+    load_cam(cam16, W, H, &cam);
+    load_cfg(cfg8, deg, &cfg);
+    if (build_scene(N, v, o, sigma, sh, &cam, &cfg, &S)) return -1;
+    if (!pix) npix = (int64_t)W * H;
+    for (int i = 0; i < N; ++i) { maxw[i] = 0.0; npx[i] = 0; }
+    const int cap = S.nvis > 0 ? S.nvis : 1;
+#pragma omp parallel
+    {
+        double* lw = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+        int* ln = (int*)calloc((size_t)(N > 0 ? N : 1), sizeof(int));
+        frag* fr = (frag*)malloc(sizeof(frag) * (size_t)cap);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < npix; ++p) {
+            int64_t lin = pix ? pix[p] : p;
+            double px = (double)(lin % W) + 0.5, py = (double)(lin / W) + 0.5;
+            pixout po;
+            int nf = 0;
+            shade_pixel(&S, &cfg, px, py, &po, fr, cap, &nf);
+            for (int f = 0; f < nf; ++f) {
+                const int i = fr[f].tri;
+                const double wt = fr[f].T * S.tri[i].o;
+                if (wt > lw[i]) lw[i] = wt;
+                ln[i] += 1;
+            }
+        }
+#pragma omp critical
+        for (int i = 0; i < N; ++i) {
+            if (lw[i] > maxw[i]) maxw[i] = lw[i];
+            npx[i] += ln[i];
+        }
+        free(lw); free(ln); free(fr);
+    }
+    free_scene(&S);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Analytic gradient (FP64)                                                  */
 /* ------------------------------------------------------------------------ */

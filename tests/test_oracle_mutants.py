@@ -16,6 +16,7 @@ from oracle import oracle as O
 import test_oracle_bin as TB
 import test_oracle_composite as TC
 import test_oracle_grad as TG
+import test_oracle_prune as TP
 import test_oracle_sh as TS
 import test_oracle_window as TW
 
@@ -51,6 +52,9 @@ PINS = [
     ("fd clamp", TG.test_fd_clamped_and_terminated),
     ("tight box", lambda: TW.test_tight_box_brute_force(0)),
     ("over", lambda: TC.test_textbook_over_operator(3)),
+    ("prune single", TP.test_single_triangle),
+    ("prune stack", TP.test_stack_with_termination),
+    ("prune order", TP.test_front_back_order_and_sample),
 ]
 
 # (label, exact source text, replacement)
@@ -110,6 +114,12 @@ MUTANTS = [
     ("grad: normal jacobian sign", "const double jx = T->sgn * (-wy / l - ex * Re_w / (l * l * l));",
      "const double jx = T->sgn * (wy / l - ex * Re_w / (l * l * l));"),
     ("grad: area derivative", "{q1[1] - q2[1], q2[0] - q1[0]},", "{q2[1] - q1[1], q2[0] - q1[0]},"),
+    ("prune weight after blending", "const double wt = fr[f].T * S.tri[i].o;",
+     "const double wt = fr[f].T * (1.0 - fr[f].a) * S.tri[i].o;"),
+    ("prune weight alpha for o", "const double wt = fr[f].T * S.tri[i].o;",
+     "const double wt = fr[f].T * fr[f].a;"),
+    ("prune sum for max", "if (lw[i] > maxw[i]) maxw[i] = lw[i];",
+     "maxw[i] += lw[i];"),
 ]
 
 
