@@ -8,7 +8,7 @@ workload (SH degree 3, 70% dense clusters + 30% background shell,
 gradient resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--view 0|1] [--no-cpu-baseline]
-                  [--no-serve] [--no-other-view]
+                  [--no-serve] [--no-other-view] [--no-prune-stats]
 """
 from __future__ import annotations
 
@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-other-view", action="store_true",
                     help="skip the second 3M-triangle view (1600x1040 for pose 0)")
+    ap.add_argument("--no-prune-stats", action="store_true",
+                    help="skip timing the forward that keeps the pruning statistics")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,4000,8000",
                     help="req/s; the quoted 200-2000 plus two rates past saturation")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -312,6 +314,30 @@ def main():
                            "projection state, lists, images); the backward keeps 8 B per pixel "
                            "(T_final, last) and no per-fragment state"},
     }
+    if not args.no_prune_stats:
+        # the forward raster that also keeps the pruning statistics (Sec. 3.2),
+        # plus the per-view count, against the plain forward of the same view
+        from paper_2505_19175_amd.render import PruneStats
+        ps = PruneStats(N, device=dev)
+        reps = 20
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * reps)]
+        for k in range(reps + 2):
+            r = k - 2
+            if r >= 0: ev[3 * r].record(stream)
+            B.ts_render_forward_stats(st.proj, st.bins, ccam, ccfg, out.rgb, out.alpha, out.depth,
+                                      out.T_final, out.last, ps.c, sh_)
+            if r >= 0: ev[3 * r + 1].record(stream)
+            B.ts_prune_count_views(ps.pixels, ps.views, N, sh_)
+            if r >= 0: ev[3 * r + 2].record(stream)
+        torch.cuda.synchronize()
+        fwd_s = float(np.mean([ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(reps)]))
+        cnt_s = float(np.mean([ev[3 * r + 1].elapsed_time(ev[3 * r + 2]) for r in range(reps)]))
+        res["prune_stats"] = {
+            "raster_fwd_stats_ms": round(fwd_s, 4), "count_views_ms": round(cnt_s, 4),
+            "raster_fwd_ms": stage_ms["raster_fwd"],
+            "overhead_frac": round((fwd_s + cnt_s) / stage_ms["raster_fwd"] - 1.0, 4),
+            "triangles_rendered_gt1px": int((ps.views > 0).sum().item())}
+        del ps
     if not args.no_other_view:
         ov = 1 - args.view if args.view in (0, 1) else 1
         cam2 = wl.cameras[ov]

@@ -179,6 +179,35 @@ int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera*
                       float* T_final, uint32_t* last, hipStream_t stream);
 
 /*
+ * Per-triangle pruning statistics (Sec. 3.2, "Pruning": a triangle whose
+ * largest blending weight T*o over the training views stays below a
+ * threshold is pruned, and so is one rendered with more than one pixel in
+ * fewer than two views).  Device arrays of N entries, caller-initialised:
+ *   max_weight  max(existing value, largest T*o at a fragment of the triangle
+ *               that is composited; T the transmittance in front of it);
+ *               non-negative, zero-fill for a fresh count
+ *   pixels      += the number of pixels where the triangle is composited
+ */
+typedef struct ts_prune_stats {
+    float* max_weight;
+    uint32_t* pixels;
+} ts_prune_stats;
+
+/* ts_render_forward that also accumulates the pruning statistics of the
+ * view into *stats, indexed by triangle (N entries each, N of the
+ * projection).  Max and add atomics: the result does not depend on the order
+ * of the tiles.  TS_EINVAL if stats or either of its arrays is NULL. */
+int ts_render_forward_stats(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                            const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                            float* T_final, uint32_t* last, const ts_prune_stats* stats,
+                            hipStream_t stream);
+
+/* After each view: views[i] += (pixels[i] > 1), then pixels[i] = 0, so views
+ * counts the views that rendered triangle i with more than one pixel.  Device
+ * arrays of N entries; TS_EINVAL if N < 0 or (N > 0 and either is NULL). */
+int ts_prune_count_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream);
+
+/*
  * Backward pass (end-to-end gradients, Sec. 3.3): reverse traversal of each
  * pixel's composited fragments, transmittance recovered from T_final (no
  * per-fragment state), per-wavefront reduction before atomics into

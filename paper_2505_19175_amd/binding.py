@@ -24,7 +24,8 @@ TS_G2D_STRIDE = 16
 TS_CGRAD_STRIDE = 12
 
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
-           "ts_bin_sort", "ts_render_forward", "ts_render_backward", "ts_raster_backward",
+           "ts_bin_sort", "ts_render_forward", "ts_render_forward_stats",
+           "ts_prune_count_views", "ts_render_backward", "ts_raster_backward",
            "ts_project_backward", "ts_batch_layout", "ts_batch_workspace_bytes",
            "ts_render_forward_batched", "ts_error_string", "ts_last_error")
 
@@ -60,6 +61,10 @@ class ts_bins(ctypes.Structure):
                 ("blocks", ctypes.c_void_p)]
 
 
+class ts_prune_stats(ctypes.Structure):
+    _fields_ = [("max_weight", ctypes.c_void_p), ("pixels", ctypes.c_void_p)]
+
+
 class ts_view(ctypes.Structure):
     _fields_ = [("cam", ts_camera), ("tile_offset", ctypes.c_uint32), ("tiles_x", ctypes.c_uint32),
                 ("pixel_offset", ctypes.c_uint64)]
@@ -92,6 +97,11 @@ def load():
     L.ts_bin_sort.argtypes = [PP, I64, PC, P, ctypes.c_size_t, PB, P, P]
     L.ts_render_forward.restype = ctypes.c_int
     L.ts_render_forward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
+    L.ts_render_forward_stats.restype = ctypes.c_int
+    L.ts_render_forward_stats.argtypes = [PP, PB, PC, PG, P, P, P, P, P,
+                                          ctypes.POINTER(ts_prune_stats), P]
+    L.ts_prune_count_views.restype = ctypes.c_int
+    L.ts_prune_count_views.argtypes = [P, P, I64, P]
     L.ts_render_backward.restype = ctypes.c_int
     L.ts_render_backward.argtypes = [P, P, P, P, I64, PP, PB, PC, PG, P, P, P, P, P, P, P, P, P, P]
     L.ts_raster_backward.restype = ctypes.c_int
@@ -163,6 +173,20 @@ def ts_render_forward(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_conf
     _check(load().ts_render_forward(ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(cam),
                                     ctypes.byref(cfg), _ptr(rgb), _ptr(alpha), _ptr(depth),
                                     _ptr(T_final), _ptr(last), stream), "ts_render_forward")
+
+
+def ts_render_forward_stats(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config, rgb,
+                            alpha, depth, T_final, last, stats: ts_prune_stats, stream: int = 0):
+    _check(load().ts_render_forward_stats(ctypes.byref(proj), ctypes.byref(bins),
+                                          ctypes.byref(cam), ctypes.byref(cfg), _ptr(rgb),
+                                          _ptr(alpha), _ptr(depth), _ptr(T_final), _ptr(last),
+                                          ctypes.byref(stats), stream),
+           "ts_render_forward_stats")
+
+
+def ts_prune_count_views(pixels, views, N: int, stream: int = 0):
+    _check(load().ts_prune_count_views(_ptr(pixels), _ptr(views), N, stream),
+           "ts_prune_count_views")
 
 
 def ts_render_backward(v, o, sigma, sh, N: int, proj: ts_proj, bins: ts_bins, cam: ts_camera,

@@ -141,22 +141,60 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
     return TS_OK;
 }
 
+}  // extern "C"
+
+static int render_forward(const char* name, const ts_proj* proj, const ts_bins* bins,
+                          const ts_camera* cam, const ts_config* cfg, float* rgb, float* alpha,
+                          float* depth, float* T_final, uint32_t* last,
+                          const ts_prune_stats* stats, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    char msg[160];
+    if (!cam_ok(cam)) return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: bad camera", name), msg));
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: bad config", name), msg));
+    if (!bins_ok(bins) || !proj || !proj->rec)
+        return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: bad projection or bins", name), msg));
+    if (!rgb || !alpha || !depth || !T_final || !last)
+        return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: null output", name), msg));
+    if (stats && (!stats->max_weight || !stats->pixels))
+        return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: null statistics", name), msg));
+    ts::launch_raster_forward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
+                              to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
+                              rgb, alpha, depth, T_final, last, bins->blocks,
+                              stats ? stats->max_weight : nullptr,
+                              stats ? stats->pixels : nullptr, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, name);
+}
+
+extern "C" {
+
 int ts_render_forward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
                       const ts_config* cfg, float* rgb, float* alpha, float* depth,
                       float* T_final, uint32_t* last, hipStream_t stream)
 {
+    return render_forward("ts_render_forward", proj, bins, cam, cfg, rgb, alpha, depth, T_final,
+                          last, nullptr, stream);
+}
+
+int ts_render_forward_stats(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                            const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                            float* T_final, uint32_t* last, const ts_prune_stats* stats,
+                            hipStream_t stream)
+{
+    if (!stats) return fail(TS_EINVAL, "ts_render_forward_stats: null statistics");
+    return render_forward("ts_render_forward_stats", proj, bins, cam, cfg, rgb, alpha, depth,
+                          T_final, last, stats, stream);
+}
+
+int ts_prune_count_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream)
+{
     g_msg[0] = 0;
-    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_render_forward: bad camera");
-    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_forward: bad config");
-    if (!bins_ok(bins) || !proj || !proj->rec)
-        return fail(TS_EINVAL, "ts_render_forward: bad projection or bins");
-    if (!rgb || !alpha || !depth || !T_final || !last)
-        return fail(TS_EINVAL, "ts_render_forward: null output");
-    ts::launch_raster_forward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
-                              to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
-                              rgb, alpha, depth, T_final, last, bins->blocks, stream);
+    if (N < 0 || (N > 0 && (!pixels || !views)))
+        return fail(TS_EINVAL, "ts_prune_count_views: bad arguments");
+    ts::launch_prune_views(pixels, views, N, stream);
     const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward");
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_prune_count_views");
 }
 
 int ts_render_backward(const float* v, const float* o, const float* sigma, const float* sh,

@@ -33,6 +33,7 @@ struct Stage {
     uint16_t hit[kBatch];        // bit 4 w + g: may composite in block g of quadrant w
     uint8_t list[16][kBatch];    // per block 4 w + g: its entries of the batch, in order
     uint32_t comp[kBatch / 2];   // forward: blocks where each entry composited, 16 bits each
+    uint32_t tri[kBatch];        // triangle (entry) index of each staged entry
 };
 
 union RecView {
@@ -210,6 +211,30 @@ __device__ __forceinline__ Pix pixel_of(int tx, int ty)
     return P;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
+}
+
+// Largest value over the 16 lanes of each DPP row (quad swaps, then the
+// half-row and row mirrors).
+__device__ __forceinline__ float row_max_f(float x)
+{
+    x = fmaxf(x, dpp<0xB1>(x));    // quad_perm [1,0,3,2]
+    x = fmaxf(x, dpp<0x4E>(x));    // quad_perm [2,3,0,1]
+    x = fmaxf(x, dpp<0x141>(x));   // row_half_mirror
+    x = fmaxf(x, dpp<0x140>(x));   // row_mirror
+    return x;
+}
+
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
@@ -224,6 +249,8 @@ struct TileJob {
     float* T;
     uint32_t* last;
     uint16_t* blocks;   // per list entry: blocks where it composited (null: not kept)
+    float* max_weight;  // pruning statistics (null: not kept): largest T*o per triangle,
+    uint32_t* pixels;   // and pixels where it is composited
 };
 
 __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
@@ -244,8 +271,11 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     for (uint32_t b = start; b < end; b += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b);
         __syncthreads();
-        if (tid < n)
-            S.hit[tid] = (uint16_t)stage_rec(S, rec, vals[b + tid], J.tx * kTile, J.ty * kTile);
+        if (tid < n) {
+            const uint32_t tri = vals[b + tid];
+            S.tri[tid] = tri;
+            S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, J.tx * kTile, J.ty * kTile);
+        }
         if (tid < kBatch / 2) S.comp[tid] = 0u;
         __syncthreads();
         const Lens L = build_lists(S, n, P.w, lane, n, n, n, n);
@@ -270,6 +300,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             const bool stop = contrib && Tn < cfg.T_min;
             const bool comp = contrib && !stop;
             const float wgt = comp ? f.a * T : 0.f;
+            const float tw = comp ? T * r.o : 0.f;   // blending weight T*o (pruning)
             C0 = fmaf(wgt, r.rgb[0], C0);
             C1 = fmaf(wgt, r.rgb[1], C1);
             C2 = fmaf(wgt, r.rgb[2], C2);
@@ -277,10 +308,19 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             T = comp ? Tn : T;
             last = comp ? b - start + (uint32_t)j + 1u : last;
             done = done || stop;
-            if (J.blocks) {   // mark the entry's block if any pixel of the row composited it
+            if (J.blocks || J.max_weight) {
                 const uint64_t cm = __ballot(comp);
-                if (P.i == 0 && ((cm >> (16 * P.g)) & 0xffffull) != 0ull)
+                const uint32_t rowbits = (uint32_t)(cm >> (16 * P.g)) & 0xffffu;
+                if (J.blocks && P.i == 0 && rowbits != 0u)   // the entry composited in this block
                     atomicOr(&S.comp[jl >> 1], my_bit << (16 * (jl & 1)));
+                if (J.max_weight) {   // pruning statistics of the row's entry
+                    const float mw = row_max_f(tw);
+                    if (P.i == 0 && rowbits != 0u) {
+                        const uint32_t tri = S.tri[jl];
+                        atomicMax(reinterpret_cast<int*>(J.max_weight + tri), __float_as_int(mw));
+                        atomicAdd(J.pixels + tri, (uint32_t)__popc(rowbits));
+                    }
+                }
             }
         }
         const bool all_done = __syncthreads_and(done);
@@ -305,13 +345,15 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
     int tiles_x, int num_tiles, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
     float* __restrict__ out_depth, float* __restrict__ out_T, uint32_t* __restrict__ out_last,
-    uint16_t* __restrict__ out_blocks)
+    uint16_t* __restrict__ out_blocks, float* __restrict__ max_weight,
+    uint32_t* __restrict__ pixels)
 {
     __shared__ Stage S;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
     TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
-              ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last, out_blocks};
+              ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last, out_blocks,
+              max_weight, pixels};
     fwd_tile(rec, vals, cfg, J, S);
 }
 
@@ -344,7 +386,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
         const int64_t po = (int64_t)V.pixel_offset;
         TileJob J{(int)(local % V.tiles_x), (int)(local / V.tiles_x), V.cam.width, V.cam.height,
                   ranges[2 * t], ranges[2 * t + 1], out_rgb + 3 * po, out_alpha + po,
-                  out_depth + po, nullptr, nullptr, nullptr};
+                  out_depth + po, nullptr, nullptr, nullptr, nullptr, nullptr};
         fwd_tile(rec, vals, cfg, J, S);
     }
 }
@@ -352,19 +394,6 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float x)
-{
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
-}
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_u(uint32_t x)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
-}
 
 // Sum 16 per-lane values over the 16 lanes of each DPP row by
 // transpose-and-add: each step pairs lanes across one bit of the lane index
@@ -418,7 +447,6 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
     const uint16_t* __restrict__ blocks, float* __restrict__ g2d)
 {
     __shared__ Stage S;
-    __shared__ uint32_t s_tri[kBatch];
     __shared__ uint32_t s_max;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
@@ -466,7 +494,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         __syncthreads();
         if (tid < n) {
             const uint32_t tri = vals[start + lo_ + tid];
-            s_tri[tid] = tri;
+            S.tri[tid] = tri;
             if (blocks) {   // the forward's record of where the entry composited
                 stage_copy(S, rec, tri, tx * kTile, ty * kTile);
                 S.hit[tid] = blocks[start + lo_ + tid];
@@ -531,7 +559,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             v[8] = f.k == 2 ? gu : 0.f;
             const float tot = row_reduce16(v, P.i);
             if (j >= 0 && P.i < 15 && tot != 0.f)
-                unsafeAtomicAdd(g2d + (int64_t)s_tri[jc] * TS_G2D_STRIDE + P.i, tot);
+                unsafeAtomicAdd(g2d + (int64_t)S.tri[jc] * TS_G2D_STRIDE + P.i, tot);
         }
         hi_ = lo_;
     }
@@ -540,11 +568,29 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                            const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
                            int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
-                           uint32_t* last, uint16_t* blocks, hipStream_t stream)
+                           uint32_t* last, uint16_t* blocks, float* max_weight, uint32_t* pixels,
+                           hipStream_t stream)
 {
     hipLaunchKernelGGL(k_raster_fwd, dim3(num_tiles), dim3(kBlock), 0, stream,
                        reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks);
+                       tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks, max_weight,
+                       pixels);
+}
+
+__global__ __launch_bounds__(256) void k_prune_views(uint32_t* __restrict__ pixels,
+                                                     uint32_t* __restrict__ views, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    views[i] += pixels[i] > 1u ? 1u : 0u;
+    pixels[i] = 0u;
+}
+
+void launch_prune_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream)
+{
+    if (N > 0)
+        hipLaunchKernelGGL(k_prune_views, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream,
+                           pixels, views, N);
 }
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,

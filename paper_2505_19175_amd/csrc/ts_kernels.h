@@ -68,7 +68,11 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
 void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                            const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
                            int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
-                           uint32_t* last, uint16_t* blocks, hipStream_t stream);
+                           uint32_t* last, uint16_t* blocks, float* max_weight, uint32_t* pixels,
+                           hipStream_t stream);
+
+// views[i] += pixels[i] > 1; pixels[i] = 0.
+void launch_prune_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream);
 
 void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                                  const uint32_t* order, const ts_view* views,

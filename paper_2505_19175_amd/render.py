@@ -81,6 +81,24 @@ class ViewState:
                        torch.empty((H, W), dtype=torch.int32, device=dev))
 
 
+class PruneStats:
+    """Pruning statistics over the views rendered with them (Sec. 3.2,
+    "Pruning"): per triangle the largest blending weight T*o and the number
+    of views that rendered it with more than one pixel."""
+
+    def __init__(self, N: int, device="cuda"):
+        n = max(N, 1)
+        self.max_weight = torch.zeros(n, dtype=torch.float32, device=device)
+        self.pixels = torch.zeros(n, dtype=torch.int32, device=device)   # per view, cleared
+        self.views = torch.zeros(n, dtype=torch.int32, device=device)
+        self.c = B.ts_prune_stats(self.max_weight.data_ptr(), self.pixels.data_ptr())
+
+    def prune_mask(self, tau_prune: float, min_views: int = 2):
+        """Triangles to prune: largest weight below tau_prune, or rendered with
+        more than one pixel in fewer than min_views views."""
+        return (self.max_weight < tau_prune) | (self.views < min_views)
+
+
 class Rasterizer:
     """Runs the four library calls for one camera."""
 
@@ -111,13 +129,18 @@ class Rasterizer:
             st.M, st.N_v = int(st.count[0]), int(st.count[1])
 
     def forward(self, st: ViewState, scene_t, cam, out: Optional[Outputs] = None,
-                sync: bool = True) -> Outputs:
+                sync: bool = True, stats: Optional["PruneStats"] = None) -> Outputs:
         ccam = self.project(st, scene_t, cam)
         self.bin_sort(st, ccam, sync=sync)
         if out is None:
             out = st.outputs()
-        B.ts_render_forward(st.proj, st.bins, ccam, self.ccfg, out.rgb, out.alpha, out.depth,
-                            out.T_final, out.last, _stream())
+        if stats is None:
+            B.ts_render_forward(st.proj, st.bins, ccam, self.ccfg, out.rgb, out.alpha, out.depth,
+                                out.T_final, out.last, _stream())
+        else:
+            B.ts_render_forward_stats(st.proj, st.bins, ccam, self.ccfg, out.rgb, out.alpha,
+                                      out.depth, out.T_final, out.last, stats.c, _stream())
+            B.ts_prune_count_views(stats.pixels, stats.views, st.N, _stream())
         st.ccam = ccam
         return out
 
