@@ -42,7 +42,8 @@ def _configure(L):
     P = ctypes.c_void_p
     L.oracle_setup.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
                                ctypes.c_int, P, P, P, P, P, P, P, P, P, P, P]
-    L.oracle_window.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
+    L.oracle_window.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int, P, P]
     L.oracle_sh.argtypes = [ctypes.c_int, P, P, P]
     L.oracle_render.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
                                 ctypes.c_int, P, ctypes.c_int64, P, P, P, P, P, P, P, P]
@@ -104,9 +105,10 @@ def _cam16(cam) -> np.ndarray:
     return np.ascontiguousarray(np.concatenate([R, t, rest]))
 
 
-def _cfg8(cfg) -> np.ndarray:
+def _cfg9(cfg) -> np.ndarray:
     vals = [cfg.alpha_min, cfg.alpha_max, cfg.T_min, cfg.z_near, cfg.r_min] + list(cfg.bg)
-    return np.ascontiguousarray(np.array(vals, np.float32).astype(np.float64))
+    out = np.array(vals, np.float32).astype(np.float64)
+    return np.ascontiguousarray(np.append(out, float(getattr(cfg, "window", 0))))
 
 
 def _scene_arrays(scene):
@@ -137,19 +139,21 @@ def setup(scene, cam, cfg) -> dict:
                key=np.zeros(N, np.float32), rgb=np.zeros((N, 3)),
                rect=np.zeros((N, 4), np.int32), ntiles=np.zeros(N, np.int32))
     rc = lib().oracle_setup(N, _p(v), _p(o), _p(s), _p(sh), _deg(scene, cfg), _p(_cam16(cam)),
-                            cam.width, cam.height, _p(_cfg8(cfg)), _p(out["vis"]), _p(out["q"]),
+                            cam.width, cam.height, _p(_cfg9(cfg)), _p(out["vis"]), _p(out["q"]),
                             _p(out["r"]), _p(out["s"]), _p(out["phis"]), _p(out["zc"]),
                             _p(out["key"]), _p(out["rgb"]), _p(out["rect"]), _p(out["ntiles"]))
     assert rc == 0
     return out
 
 
-def window(q, p, sigma: float):
-    """(u, I) at point p for one 2D triangle q[3,2] (Eq. 1)."""
+def window(q, p, sigma: float, window: int = 0):
+    """(u, I) at point p for one 2D triangle q[3,2]: window 0 is Eq. 1
+    (u = phi(p)/phi(s)), 1 the sigmoid of Eq. 2 (u = phi(p)), 2 Eq. 1 with
+    the LogSumExp SDF (u = phi_lse(p)/phi_lse(s))."""
     q6 = _d(q).reshape(6)
     u = ctypes.c_double()
     I = ctypes.c_double()
-    lib().oracle_window(_p(q6), float(p[0]), float(p[1]), float(sigma),
+    lib().oracle_window(_p(q6), float(p[0]), float(p[1]), float(sigma), int(window),
                         ctypes.byref(u), ctypes.byref(I))
     return u.value, I.value
 
@@ -180,7 +184,7 @@ def render(scene, cam, cfg, pix: Optional[np.ndarray] = None) -> dict:
     flag = np.zeros(npix, np.int32)
     hsh = np.zeros(npix, np.uint64)
     rc = lib().oracle_render(N, _p(v), _p(o), _p(s), _p(sh), _deg(scene, cfg), _p(_cam16(cam)),
-                             cam.width, cam.height, _p(_cfg8(cfg)), npix, _p(pixa), _p(rgb),
+                             cam.width, cam.height, _p(_cfg9(cfg)), npix, _p(pixa), _p(rgb),
                              _p(alpha), _p(depth), _p(Tf), _p(nfrag), _p(flag), _p(hsh))
     assert rc == 0
     out = dict(rgb=rgb.reshape(3, npix), alpha=alpha, depth=depth, T_final=Tf,
@@ -202,7 +206,7 @@ def prune_stats(scene, cam, cfg, pix: Optional[np.ndarray] = None) -> dict:
     maxw = np.zeros(max(N, 1))
     npx = np.zeros(max(N, 1), np.int32)
     rc = lib().oracle_prune_stats(N, _p(v), _p(o), _p(s), _p(sh), _deg(scene, cfg),
-                                  _p(_cam16(cam)), cam.width, cam.height, _p(_cfg8(cfg)), npix,
+                                  _p(_cam16(cam)), cam.width, cam.height, _p(_cfg9(cfg)), npix,
                                   _p(pixa), _p(maxw), _p(npx))
     assert rc == 0
     return dict(max_weight=maxw[:N], pixels=npx[:N])
@@ -224,7 +228,7 @@ def backward(scene, cam, cfg, dC, dA=None, dD=None, pix: Optional[np.ndarray] = 
     gs = np.zeros(N)
     gsh = np.zeros(N * K * 3)
     rc = lib().oracle_backward(N, _p(v), _p(o), _p(s), _p(sh), _deg(scene, cfg), _p(_cam16(cam)),
-                               cam.width, cam.height, _p(_cfg8(cfg)), npix, _p(pixa), _p(dCf),
+                               cam.width, cam.height, _p(_cfg9(cfg)), npix, _p(pixa), _p(dCf),
                                _p(dAf), _p(dDf), _p(gv), _p(go), _p(gs), _p(gsh))
     assert rc == 0
     return dict(v=gv.reshape(N, 3, 3), o=go, sigma=gs, sh=gsh.reshape(N, K, 3))

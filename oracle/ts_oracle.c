@@ -12,6 +12,10 @@
  *   - the 2D signed distance phi(p) = max_k (n_k . p + d_k), unit outward
  *     normals n_k, and its value phi(s) at the incentre s            (Sec. 3.1, "A new window function")
  *   - the window I(p) = ReLU(phi(p)/phi(s))^sigma                    (Eq. 1)
+ *   - the two alternatives the paper discusses and sets aside: the
+ *     sigmoid window I(p) = sigmoid(-phi(p)/sigma), and the SDF with the
+ *     max replaced by LogSumExp, phi(p) = log sum_k exp L_k(p), inside
+ *     the window of Eq. 1                                            (Sec. 3.1, discussion; Eq. 2)
  *   - front-to-back alpha blending in depth order with I as opacity
  *     modulated by o (the blending weight T*o of Sec. 3.2)           (Sec. 3.1)
  *   - depth order by the triangle centre                             (Supp., "Depth sorting")
@@ -52,9 +56,12 @@ typedef struct {
     int W, H;
 } ocam;
 
-/* cfg[8] = alpha_min, alpha_max, T_min, z_near, r_min, bg[3] */
+/* cfg[9] = alpha_min, alpha_max, T_min, z_near, r_min, bg[3], window */
+enum { WIN_PAPER = 0, WIN_SIGMOID = 1, WIN_LSE = 2 };
+
 typedef struct {
     double alpha_min, alpha_max, T_min, z_near, r_min, bg[3];
+    int window;         /* WIN_PAPER (Eq. 1), WIN_SIGMOID (Eq. 2), WIN_LSE */
     int deg;
     double band_alpha, band_T; /* widths of the "decision too close to call" flags */
 } ocfg;
@@ -72,6 +79,7 @@ static void load_cfg(const double* g, int deg, ocfg* cfg)
     cfg->alpha_min = g[0]; cfg->alpha_max = g[1]; cfg->T_min = g[2];
     cfg->z_near = g[3]; cfg->r_min = g[4];
     cfg->bg[0] = g[5]; cfg->bg[1] = g[6]; cfg->bg[2] = g[7];
+    cfg->window = (int)g[8];
     cfg->deg = deg;
     cfg->band_alpha = 1e-6;
     cfg->band_T = 5e-9;
@@ -196,6 +204,7 @@ typedef struct {
     double d[3];        /* offsets: L_k(p) = n_k . p + d_k */
     double s[2];        /* incentre */
     double phis;        /* phi(s) */
+    double phis_lse;    /* LogSumExp SDF at s (WIN_LSE) */
     double r;           /* inradius */
     double zc;          /* depth of the centre */
     float key;          /* depth sort key */
@@ -217,6 +226,22 @@ static double phi_at(const otri* T, double px, double py, int* kmax)
     }
     if (kmax) *kmax = best;
     return m;
+}
+
+/* The SDF with the max replaced by LogSumExp: log sum_k exp L_k(p), written
+ * as m + log sum_k exp(L_k - m) with m = max_k L_k so no term overflows;
+ * w[k] (if not NULL) receives the softmax weights dphi/dL_k. */
+static double lse_at(const otri* T, double px, double py, double w[3])
+{
+    double L[3], m = -1e300, sum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        L[k] = T->n[k][0] * px + T->n[k][1] * py + T->d[k];
+        if (L[k] > m) m = L[k];
+    }
+    for (int k = 0; k < 3; ++k) sum += exp(L[k] - m);
+    if (w)
+        for (int k = 0; k < 3; ++k) w[k] = exp(L[k] - m) / sum;
+    return m + log(sum);
 }
 
 static void setup_tri(const double* v, double o, double sigma, const double* sh,
@@ -255,7 +280,9 @@ static void setup_tri(const double* v, double o, double sigma, const double* sh,
     T->area2 = T->e[0][0] * (T->q[2][1] - T->q[0][1]) - T->e[0][1] * (T->q[2][0] - T->q[0][0]);
     T->sgn = T->area2 >= 0.0 ? 1.0 : -1.0;
     T->r = T->perim > 0.0 ? fabs(T->area2) / T->perim : 0.0;
-    if (!(T->r >= cfg->r_min) || !(o >= cfg->alpha_min)) { T->visible = 0; return; }
+    /* the sigmoid stays below 1, so it needs o > alpha_min strictly */
+    const int o_ok = cfg->window == WIN_SIGMOID ? o > cfg->alpha_min : o >= cfg->alpha_min;
+    if (!(T->r >= cfg->r_min) || !o_ok) { T->visible = 0; return; }
 
     /* edge lines with unit normals pointing out of the triangle */
     for (int k = 0; k < 3; ++k) {
@@ -267,6 +294,11 @@ static void setup_tri(const double* v, double o, double sigma, const double* sh,
     T->s[0] = (T->len[1] * T->q[0][0] + T->len[2] * T->q[1][0] + T->len[0] * T->q[2][0]) / T->perim;
     T->s[1] = (T->len[1] * T->q[0][1] + T->len[2] * T->q[1][1] + T->len[0] * T->q[2][1]) / T->perim;
     T->phis = phi_at(T, T->s[0], T->s[1], NULL);
+    if (cfg->window == WIN_LSE) {
+        /* a triangle whose LogSumExp SDF is not negative at s has no inside */
+        T->phis_lse = lse_at(T, T->s[0], T->s[1], NULL);
+        if (!(T->phis_lse < 0.0)) { T->visible = 0; return; }
+    }
 
     /* colour: SH along the direction from the camera centre to the centroid */
     double cc[3], cen[3];
@@ -288,10 +320,27 @@ static void setup_tri(const double* v, double o, double sigma, const double* sh,
     /* tight bounding box (Supp., "Tile assignment"): move every edge line
      * inward by d = L(s) (tau/o)^(1/sigma), with L(s) = -phi(s) the distance
      * from the edges to the incentre; the shrunk triangle's corners are the
-     * pairwise intersections of consecutive moved lines. */
-    double dist = -T->phis * pow(cfg->alpha_min / o, 1.0 / sigma);
+     * pairwise intersections of consecutive moved lines.
+     * Sigmoid window: o sigmoid(-phi/sigma) >= tau where
+     * phi <= sigma log(o/tau - 1), so the lines move by d = -sigma log(o/tau - 1)
+     * (outward when d < 0); nothing is left when d >= r.
+     * LogSumExp SDF: it is at least the max, so {o I >= tau} lies inside
+     * {phi <= phi_lse(s) (tau/o)^(1/sigma)}: d = -phi_lse(s) (tau/o)^(1/sigma). */
+    double dist;
+    if (cfg->window == WIN_SIGMOID) {
+        dist = -sigma * log(o / cfg->alpha_min - 1.0);
+        if (!(dist < T->r)) { T->visible = 0; return; }
+    } else if (cfg->window == WIN_LSE) {
+        dist = -T->phis_lse * pow(cfg->alpha_min / o, 1.0 / sigma);
+    } else {
+        dist = -T->phis * pow(cfg->alpha_min / o, 1.0 / sigma);
+    }
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-    for (int k = 0; k < 3; ++k) {
+    if (isinf(dist)) {   /* sigmoid with alpha_min = 0: unbounded support */
+        xmin = ymin = -1e300;
+        xmax = ymax = 1e300;
+    }
+    for (int k = 0; k < 3 && !isinf(dist); ++k) {
         int j = (k + 2) % 3;                 /* edges j and k meet at vertex k */
         double a1 = T->n[j][0], b1 = T->n[j][1], c1 = -(T->d[j] + dist);
         double a2 = T->n[k][0], b2 = T->n[k][1], c2 = -(T->d[k] + dist);
@@ -400,9 +449,16 @@ static void shade_pixel(const oscene* S, const ocfg* cfg, double px, double py,
         const otri* tr = &S->tri[i];
         int k;
         double phi = phi_at(tr, px, py, &k);
-        double u = phi / tr->phis;
-        if (!(u > 0.0)) continue;
-        double I = pow(u, tr->sigma);
+        double u, I;
+        if (cfg->window == WIN_SIGMOID) {          /* Eq. 2; u holds phi */
+            u = phi;
+            I = 1.0 / (1.0 + exp(phi / tr->sigma));
+        } else {
+            if (cfg->window == WIN_LSE) phi = lse_at(tr, px, py, NULL);
+            u = phi / (cfg->window == WIN_LSE ? tr->phis_lse : tr->phis);
+            if (!(u > 0.0)) continue;
+            I = pow(u, tr->sigma);
+        }
         double a = tr->o * I;
         int clamped = 0;
         if (a > cfg->alpha_max) { a = cfg->alpha_max; clamped = 1; }
@@ -447,12 +503,12 @@ static void shade_pixel(const oscene* S, const ocfg* cfg, double px, double py,
  *   rect[N*4], ntiles[N]. Any pointer may be NULL. */
 int oracle_setup(int N, const double* v, const double* o, const double* sigma,
                  const double* sh, int deg, const double* cam16, int W, int H,
-                 const double* cfg8, int* vis, double* q, double* r, double* s,
+                 const double* cfg9, int* vis, double* q, double* r, double* s,
                  double* phis, double* zc, float* key, double* rgb, int* rect, int* ntiles)
 {
     ocam cam; ocfg cfg;
     load_cam(cam16, W, H, &cam);
-    load_cfg(cfg8, deg, &cfg);
+    load_cfg(cfg9, deg, &cfg);
     const int K = (deg + 1) * (deg + 1);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < N; ++i) {
@@ -473,9 +529,12 @@ int oracle_setup(int N, const double* v, const double* o, const double* sigma,
     return 0;
 }
 
-/* Window at one point for one 2D triangle q[6]: returns u = phi(p)/phi(s)
- * and I = ReLU(u)^sigma. */
-int oracle_window(const double* q6, double px, double py, double sigma, double* u_out, double* I_out)
+/* Window at one point for one 2D triangle q[6].  window 0: u = phi(p)/phi(s)
+ * and I = ReLU(u)^sigma; 1: u = phi(p) and I = sigmoid(-phi(p)/sigma);
+ * 2: u = phi_lse(p)/phi_lse(s) and I = ReLU(u)^sigma (u = 0 when
+ * phi_lse(s) >= 0). */
+int oracle_window(const double* q6, double px, double py, double sigma, int window,
+                  double* u_out, double* I_out)
 {
     otri T;
     memset(&T, 0, sizeof T);
@@ -498,7 +557,19 @@ int oracle_window(const double* q6, double px, double py, double sigma, double* 
     T.s[0] = (T.len[1] * T.q[0][0] + T.len[2] * T.q[1][0] + T.len[0] * T.q[2][0]) / T.perim;
     T.s[1] = (T.len[1] * T.q[0][1] + T.len[2] * T.q[1][1] + T.len[0] * T.q[2][1]) / T.perim;
     T.phis = phi_at(&T, T.s[0], T.s[1], NULL);
-    double u = phi_at(&T, px, py, NULL) / T.phis;
+    if (window == WIN_SIGMOID) {
+        const double phi = phi_at(&T, px, py, NULL);
+        *u_out = phi;
+        *I_out = 1.0 / (1.0 + exp(phi / sigma));
+        return 0;
+    }
+    double u;
+    if (window == WIN_LSE) {
+        const double ps = lse_at(&T, T.s[0], T.s[1], NULL);
+        u = ps < 0.0 ? lse_at(&T, px, py, NULL) / ps : 0.0;
+    } else {
+        u = phi_at(&T, px, py, NULL) / T.phis;
+    }
     *u_out = u;
     *I_out = u > 0.0 ? pow(u, sigma) : 0.0;
     return 0;
@@ -517,13 +588,13 @@ int oracle_sh(int deg, const double* dir3, double* Y, double* dY)
  * channel c at rgb[c*npix + p]), alpha, depth, T_final, nfrag, flag, hash. */
 int oracle_render(int N, const double* v, const double* o, const double* sigma,
                   const double* sh, int deg, const double* cam16, int W, int H,
-                  const double* cfg8, int64_t npix, const int64_t* pix,
+                  const double* cfg9, int64_t npix, const int64_t* pix,
                   double* rgb, double* alpha, double* depth, double* T_final,
                   int* nfrag, int* flag, uint64_t* hash)
 {
     ocam cam; ocfg cfg; oscene S;
     load_cam(cam16, W, H, &cam);
-    load_cfg(cfg8, deg, &cfg);
+    load_cfg(cfg9, deg, &cfg);
     if (build_scene(N, v, o, sigma, sh, &cam, &cfg, &S)) return -1;
     if (!pix) npix = (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -552,12 +623,12 @@ int oracle_render(int N, const double* v, const double* o, const double* sigma,
  * composited). */
 int oracle_prune_stats(int N, const double* v, const double* o, const double* sigma,
                        const double* sh, int deg, const double* cam16, int W, int H,
-                       const double* cfg8, int64_t npix, const int64_t* pix,
+                       const double* cfg9, int64_t npix, const int64_t* pix,
                        double* maxw, int* npx)
 {
     ocam cam; ocfg cfg; oscene S;
     load_cam(cam16, W, H, &cam);
-    load_cfg(cfg8, deg, &cfg);
+    load_cfg(cfg9, deg, &cfg);
     if (build_scene(N, v, o, sigma, sh, &cam, &cfg, &S)) return -1;
     if (!pix) npix = (int64_t)W * H;
     for (int i = 0; i < N; ++i) { maxw[i] = 0.0; npx[i] = 0; }
@@ -653,13 +724,13 @@ static void dL_dq(const otri* T, int k, double px, double py, double g[3][2])
  * Outputs (overwritten): gv[N*9], go[N], gsig[N], gsh[N*K*3]. */
 int oracle_backward(int N, const double* v, const double* o, const double* sigma,
                     const double* sh, int deg, const double* cam16, int W, int H,
-                    const double* cfg8, int64_t npix, const int64_t* pix,
+                    const double* cfg9, int64_t npix, const int64_t* pix,
                     const double* dC, const double* dA, const double* dD,
                     double* gv, double* go, double* gsig, double* gsh)
 {
     ocam cam; ocfg cfg; oscene S;
     load_cam(cam16, W, H, &cam);
-    load_cfg(cfg8, deg, &cfg);
+    load_cfg(cfg9, deg, &cfg);
     if (build_scene(N, v, o, sigma, sh, &cam, &cfg, &S)) return -1;
     const int K = S.K;
     tacc* acc = (tacc*)calloc((size_t)(N > 0 ? N : 1), sizeof(tacc));
@@ -709,17 +780,41 @@ int oracle_backward(int N, const double* v, const double* o, const double* sigma
                 /* a = o I */
                 atomic_add(&A->go, ga * F->I);
                 const double gI = ga * tr->o;
+                double gL[3][2], gr[3][2];
+                dL_dq(tr, F->kmax, px, py, gL);
+                if (cfg.window == WIN_SIGMOID) {
+                    /* I = 1/(1 + exp(phi/sigma)), phi = L_k(p):
+                     * dI/dphi = -I(1-I)/sigma, dI/dsigma = I(1-I) phi/sigma^2 */
+                    const double s = tr->sigma, g = gI * F->I * (1.0 - F->I);
+                    atomic_add(&A->gsig, g * F->u / (s * s));
+                    for (int i = 0; i < 3; ++i)
+                        for (int c = 0; c < 2; ++c) atomic_add(&A->gq[i][c], -g / s * gL[i][c]);
+                    continue;
+                }
                 /* I = u^sigma */
                 atomic_add(&A->gsig, gI * F->I * log(F->u));
                 const double gu = gI * tr->sigma * F->I / F->u;
-                /* u = L_k(p) / phi(s),  phi(s) = -r */
-                double gL[3][2], gr[3][2];
-                dL_dq(tr, F->kmax, px, py, gL);
+                double phis = tr->phis;
+                if (cfg.window == WIN_LSE) {
+                    /* phi = log sum_k exp L_k(p): dphi = sum_k w_k dL_k (softmax
+                     * weights); at s every L_k equals -r, so phi_lse(s) =
+                     * log 3 - r and dphi_lse(s) = -dr, as for the max */
+                    double w[3], gk[3][2];
+                    lse_at(tr, px, py, w);
+                    for (int i = 0; i < 3; ++i) gL[i][0] = gL[i][1] = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        dL_dq(tr, k, px, py, gk);
+                        for (int i = 0; i < 3; ++i)
+                            for (int c = 0; c < 2; ++c) gL[i][c] += w[k] * gk[i][c];
+                    }
+                    phis = tr->phis_lse;
+                }
+                /* u = phi(p) / phi(s),  dphi(s) = -dr */
                 dr_dq(tr, gr);
                 for (int i = 0; i < 3; ++i)
                     for (int c = 0; c < 2; ++c) {
-                        /* du = (dL - u dphis)/phis, dphis = -dr */
-                        double du = (gL[i][c] + F->u * gr[i][c]) / tr->phis;
+                        /* du = (dphi - u dphis)/phis, dphis = -dr */
+                        double du = (gL[i][c] + F->u * gr[i][c]) / phis;
                         atomic_add(&A->gq[i][c], gu * du);
                     }
             }

@@ -45,6 +45,12 @@ class Camera:
                       int(self.width), int(self.height))
 
 
+# Window functions (Sec. 3.1): the paper's ReLU(phi/phi(s))^sigma (Eq. 1), and
+# the two alternatives it discusses: sigmoid(-phi/sigma) (Eq. 2) and Eq. 1
+# with the max of the SDF replaced by LogSumExp.
+WINDOW_PAPER, WINDOW_SIGMOID, WINDOW_LSE = 0, 1, 2
+
+
 @dataclasses.dataclass
 class Config:
     """Rasterizer constants.  The paper names tau_cutoff but gives no value
@@ -56,12 +62,13 @@ class Config:
     r_min: float = 1e-6              # degenerate 2D triangle cull (inradius, px)
     sh_degree: int = 3
     bg: tuple = (0.0, 0.0, 0.0)
+    window: int = 0                  # WINDOW_PAPER, WINDOW_SIGMOID or WINDOW_LSE
 
     def as_f32(self) -> "Config":
         f = lambda x: float(np.float32(x))
         return Config(f(self.alpha_min), f(self.alpha_max), f(self.T_min),
                       f(self.z_near), f(self.r_min), int(self.sh_degree),
-                      tuple(f(b) for b in self.bg))
+                      tuple(f(b) for b in self.bg), int(self.window))
 
 
 @dataclasses.dataclass

@@ -19,6 +19,7 @@ import test_oracle_grad as TG
 import test_oracle_prune as TP
 import test_oracle_sh as TS
 import test_oracle_window as TW
+import test_oracle_window_variants as TV
 
 SRC = os.path.join(os.path.dirname(O.__file__), "ts_oracle.c")
 
@@ -55,6 +56,17 @@ PINS = [
     ("prune single", TP.test_single_triangle),
     ("prune stack", TP.test_stack_with_termination),
     ("prune order", TP.test_front_back_order_and_sample),
+    ("sigmoid points", TV.test_sigmoid_at_incentre_boundary_and_outside),
+    ("lse small", TV.test_lse_small_triangle_has_no_inside),
+    ("lse points", TV.test_lse_pointwise_and_bounds),
+    ("sigmoid box", lambda: TV.test_variant_tight_box_brute_force(1, 0)),
+    ("lse box", lambda: TV.test_variant_tight_box_brute_force(2, 0)),
+    ("sigmoid render", lambda: TV.test_variant_single_triangle_closed_form(1)),
+    ("lse render", lambda: TV.test_variant_single_triangle_closed_form(2)),
+    ("sigmoid fd v", lambda: TV.test_variant_fd_gradients(1, "v")),
+    ("sigmoid fd sigma", lambda: TV.test_variant_fd_gradients(1, "sigma")),
+    ("lse fd v", lambda: TV.test_variant_fd_gradients(2, "v")),
+    ("lse fd sigma", lambda: TV.test_variant_fd_gradients(2, "sigma")),
 ]
 
 # (label, exact source text, replacement)
@@ -84,21 +96,21 @@ MUTANTS = [
     ("camera centre R not transposed",
      "cc[a] = -(cam->R[0 + a] * cam->t[0] + cam->R[3 + a] * cam->t[1] + cam->R[6 + a] * cam->t[2]);",
      "cc[a] = -(cam->R[3 * a + 0] * cam->t[0] + cam->R[3 * a + 1] * cam->t[1] + cam->R[3 * a + 2] * cam->t[2]);"),
-    ("tight box exponent", "double dist = -T->phis * pow(cfg->alpha_min / o, 1.0 / sigma);",
-     "double dist = -T->phis * pow(cfg->alpha_min / o, sigma);"),
+    ("tight box exponent", "dist = -T->phis * pow(cfg->alpha_min / o, 1.0 / sigma);",
+     "dist = -T->phis * pow(cfg->alpha_min / o, sigma);"),
     ("rect rounding", "double fx0 = ceil(xmin - 0.5), fx1 = floor(xmax - 0.5);",
      "double fx0 = floor(xmin - 0.5), fx1 = floor(xmax - 0.5);"),
     ("back-to-front order", "if (ki < kj) return -1;\n    if (ki > kj) return 1;",
      "if (ki < kj) return 1;\n    if (ki > kj) return -1;"),
     ("tie order reversed", "return (i > j) - (i < j);", "return (i < j) - (i > j);"),
-    ("window exponent", "double I = pow(u, tr->sigma);", "double I = pow(u, 1.0 / tr->sigma);"),
+    ("window exponent", "I = pow(u, tr->sigma);", "I = pow(u, 1.0 / tr->sigma);"),
     ("near plane one vertex", "if (!(T->xc[i][2] > cfg->z_near)) T->visible = 0;",
      "if (i == 0 && !(T->xc[i][2] > cfg->z_near)) T->visible = 0;"),
     ("depth weight", "D += w * tr->zc;\n        T = Tn;", "D += a * tr->zc;\n        T = Tn;"),
     ("grad: later-sum term dropped", "ga += gC[c] * (tr->rgb[c] * Ti - SC[c] / om);",
      "ga += gC[c] * (tr->rgb[c] * Ti);"),
-    ("grad: inradius sign", "double du = (gL[i][c] + F->u * gr[i][c]) / tr->phis;",
-     "double du = (gL[i][c] - F->u * gr[i][c]) / tr->phis;"),
+    ("grad: inradius sign", "double du = (gL[i][c] + F->u * gr[i][c]) / phis;",
+     "double du = (gL[i][c] - F->u * gr[i][c]) / phis;"),
     ("grad: log base", "atomic_add(&A->gsig, gI * F->I * log(F->u));",
      "atomic_add(&A->gsig, gI * F->I * log2(F->u));"),
     ("grad: camera jacobian", "gx[2] = -cam.fx * x / (z * z) * A->gq[j][0]",
@@ -120,6 +132,18 @@ MUTANTS = [
      "const double wt = fr[f].T * fr[f].a;"),
     ("prune sum for max", "if (lw[i] > maxw[i]) maxw[i] = lw[i];",
      "maxw[i] += lw[i];"),
+    ("sigmoid sign", "I = 1.0 / (1.0 + exp(phi / tr->sigma));",
+     "I = 1.0 / (1.0 + exp(-phi / tr->sigma));"),
+    ("sigmoid box outward sign", "dist = -sigma * log(o / cfg->alpha_min - 1.0);",
+     "dist = sigma * log(o / cfg->alpha_min - 1.0);"),
+    ("sigmoid grad sigma sign", "atomic_add(&A->gsig, g * F->u / (s * s));",
+     "atomic_add(&A->gsig, -g * F->u / (s * s));"),
+    ("lse normalised by max phi(s)", "u = phi / (cfg->window == WIN_LSE ? tr->phis_lse : tr->phis);",
+     "u = phi / tr->phis;"),
+    ("lse box from max phi(s)", "dist = -T->phis_lse * pow(", "dist = -T->phis * pow("),
+    ("lse softmax unnormalised", "w[k] = exp(L[k] - m) / sum;", "w[k] = exp(L[k] - m);"),
+    ("lse grad through one edge", "gL[i][c] += w[k] * gk[i][c];",
+     "gL[i][c] += (k == F->kmax) * gk[i][c];"),
 ]
 
 
