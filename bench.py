@@ -8,7 +8,8 @@ workload (SH degree 3, 70% dense clusters + 30% background shell,
 gradient resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--view 0|1] [--no-cpu-baseline]
-                  [--no-serve] [--no-other-view] [--no-prune-stats]
+                  [--no-serve] [--no-other-view] [--no-prune-stats] [--no-windows]
+                  [--no-densify] [--no-train]
 """
 from __future__ import annotations
 
@@ -177,6 +178,12 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-other-view", action="store_true",
                     help="skip the second 3M-triangle view (1600x1040 for pose 0)")
+    ap.add_argument("--no-train", action="store_true",
+                    help="skip timing the synthetic training step")
+    ap.add_argument("--no-densify", action="store_true",
+                    help="skip timing the densification kernels")
+    ap.add_argument("--no-windows", action="store_true",
+                    help="skip timing the sigmoid and LogSumExp windows")
     ap.add_argument("--no-prune-stats", action="store_true",
                     help="skip timing the forward that keeps the pruning statistics")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,4000,8000",
@@ -220,17 +227,17 @@ def main():
     sh_ = stream.cuda_stream
     ras = Rasterizer(cfg, device=dev)
 
-    def prepare(view_cam):
+    def prepare(view_cam, rasv=ras):
         """Buffers of one view; the instance list is sized once with a host
         read-back, then every step runs without one."""
         Wv, Hv = view_cam.width, view_cam.height
         stv = ViewState(N, Wv, Hv, 4 * N, device=dev)
-        outv = ras.forward(stv, scene_t, view_cam, sync=True)
+        outv = rasv.forward(stv, scene_t, view_cam, sync=True)
         stv._alloc_lists(int(stv.M * 1.05) + 4096)
         up, _, _ = synth.upstream(wl.upstream_seed, Wv, Hv)
         return stv, outv, B.make_camera(view_cam), torch.tensor(up, device=dev)
 
-    def make_step(stv, outv, ccam, dCv):
+    def make_step(stv, outv, ccam, dCv, ccfg=ccfg):
         def step(ev=None):
             if ev: ev[0].record(stream)
             B.ts_project(v, o, sg, sh, N, ccam, ccfg, stv.proj, sh_)
@@ -338,6 +345,130 @@ def main():
             "overhead_frac": round((fwd_s + cnt_s) / stage_ms["raster_fwd"] - 1.0, 4),
             "triangles_rendered_gt1px": int((ps.views > 0).sum().item())}
         del ps
+    if not args.no_windows:
+        # the two window alternatives of Sec. 3.1 on the same view
+        import dataclasses
+        res["windows"] = {}
+        for wname, wcode in (("sigmoid", synth.WINDOW_SIGMOID), ("lse", synth.WINDOW_LSE)):
+            cfg_w = dataclasses.replace(cfg, window=wcode)
+            stw, outw, ccw, dCw = prepare(cam, Rasterizer(cfg_w, device=dev))
+            msw, perw = timed(make_step(stw, outw, ccw, dCw, B.make_config(cfg_w)), 20, 3, stw)
+            res["windows"][wname] = {
+                "steps": 20, "ms_per_step": round(msw, 4),
+                "Mpixel_per_s": round(W * H / (msw * 1e-3) / 1e6, 3),
+                "N_visible": stw.N_v, "instances": stw.M,
+                "stage_ms": {s: round(float(perw[:, j].mean()), 4) for j, s in enumerate(stages)}}
+            del stw, outw, dCw
+    if not args.no_train:
+        # one synthetic training step (Sec. 3.3) on the same view: fit a copy
+        # of the soup with vertices moved by N(0, 0.002^2) to the original's
+        # render; forward, L1 + D-SSIM loss, backward, regularizers + Adam
+        import dataclasses
+        from paper_2505_19175_amd.train import TrainState
+        tgt = out.rgb.clone()
+        rng_t = np.random.default_rng(88)
+        sc_t = dataclasses.replace(wl.scene, v=(wl.scene.v + rng_t.normal(
+            0, 0.002, wl.scene.v.shape)).astype(np.float32))
+        ts = TrainState(sc_t, device=dev)
+        stt = ViewState(N, W, H, 4 * N, device=dev)
+        outt = stt.outputs()
+        ras.forward(stt, ts.scene_t(), cam, out=outt, sync=True)
+        stt._alloc_lists(int(stt.M * 1.3) + 4096)
+        gv_t, go_t, gs_t, gsh_t = ts.grads
+
+        def train_step(ev=None):
+            if ev: ev[0].record(stream)
+            ras.forward(stt, ts.scene_t(), cam, out=outt, sync=False)
+            if ev: ev[1].record(stream)
+            dCt = ts.image_loss(outt.rgb, tgt)
+            if ev: ev[2].record(stream)
+            B.ts_render_backward(ts.v, ts.o, ts.sigma, ts.sh, N, stt.proj, stt.bins, stt.ccam,
+                                 ccfg, dCt, None, None, outt.T_final, outt.last, gv_t, go_t,
+                                 gs_t, gsh_t, sh_)
+            if ev: ev[3].record(stream)
+            ts.t += 1
+            ts.opt.step = ts.t
+            B.ts_optimizer_step(ts.v, ts.a, ts.b, ts.sh, ts.o, ts.sigma, ts.deg, N, gv_t, go_t,
+                                gs_t, gsh_t, ts.state, ts.opt, sh_)
+            if ev: ev[4].record(stream)
+
+        for _ in range(3):
+            train_step()
+        torch.cuda.synchronize()
+        loss0 = ts.loss_value()
+        reps = 20
+        evt = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+        w0 = time.perf_counter()
+        for k in range(reps):
+            train_step(evt[k])
+        torch.cuda.synchronize()
+        wall_t = (time.perf_counter() - w0) / reps * 1e3
+        assert int(stt.d_count[2].item()) == 0, "instance list overflow"
+        part = np.array([[evt[k][j].elapsed_time(evt[k][j + 1]) for j in range(4)]
+                         for k in range(reps)]).mean(0)
+        ms_t = max(float(evt[0][0].elapsed_time(evt[-1][4])) / reps, wall_t)
+        K3 = 3 * K
+        opt_bytes = N * (28.0 * (9 + 2 + K3) + 132.0)
+        loss_bytes = 44.0 * 3 * W * H
+        res["train_step"] = {
+            "workload": f"tri3M_{W}x{H}: fit a copy of the soup with vertices moved by "
+                        f"N(0, 0.002^2) to the original's render",
+            "steps": reps, "ms_per_step": round(ms_t, 4),
+            "Mpixel_per_s": round(W * H / (ms_t * 1e-3) / 1e6, 3),
+            "stage_ms": {"forward": round(float(part[0]), 4), "image_loss": round(float(part[1]), 4),
+                         "backward": round(float(part[2]), 4),
+                         "optimizer": round(float(part[3]), 4)},
+            "image_loss_GBps_algorithmic": round(loss_bytes / (part[1] * 1e-3) / 1e9, 1),
+            "optimizer_GBps_algorithmic": round(opt_bytes / (part[3] * 1e-3) / 1e9, 1),
+            "loss_first": round(loss0, 6), "loss_last": round(ts.loss_value(), 6),
+            "bytes_note": "optimizer: 28 B per parameter (read p, g, m, s; write p, m, s) + "
+                          "132 B per triangle for the regularizers; image loss: 44 B per value"}
+        del ts, stt, outt, tgt
+    if not args.no_densify:
+        # densification (Sec. 3.2) on the same soup: Bernoulli selection of
+        # 10% of the triangles by inverse sigma, then midpoint subdivision
+        # in place (30% more triangles); the soup copy has room for them
+        NSH = 3 * K
+        cap = N + 3 * int(0.12 * N) + 1024
+        dv = torch.zeros((cap, 9), dtype=torch.float32, device=dev)
+        do_ = torch.zeros(cap, dtype=torch.float32, device=dev)
+        ds = torch.zeros(cap, dtype=torch.float32, device=dev)
+        dsh = torch.zeros((cap, NSH), dtype=torch.float32, device=dev)
+        dv[:N].copy_(v.reshape(N, 9)); do_[:N].copy_(o); ds[:N].copy_(sg)
+        dsh[:N].copy_(sh.reshape(N, NSH))
+        gen = np.random.default_rng(77)
+        u = torch.tensor(gen.random(N).astype(np.float32), device=dev)
+        sel = torch.empty(N, dtype=torch.uint8, device=dev)
+        dws_bytes = B.ts_densify_workspace_bytes(N)
+        dws = torch.empty(dws_bytes, dtype=torch.uint8, device=dev)
+        dcnt = torch.zeros(2, dtype=torch.int32, device=dev)
+        reps = 20
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * reps)]
+        for k in range(reps + 2):
+            r = k - 2
+            if r >= 0: ev[3 * r].record(stream)
+            B.ts_densify_select(do_, ds, N, B.TS_DENSIFY_INV_SIGMA, 0.1 * N, u, sel, dws, dws_bytes,
+                                sh_)
+            if r >= 0: ev[3 * r + 1].record(stream)
+            B.ts_densify_subdivide(dv, do_, ds, dsh, cfg.sh_degree, N, cap, sel, dws, dws_bytes,
+                                   dcnt, None, sh_)
+            if r >= 0: ev[3 * r + 2].record(stream)
+        torch.cuda.synchronize()
+        sel_ms = float(np.mean([ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(reps)]))
+        sub_ms = float(np.mean([ev[3 * r + 1].elapsed_time(ev[3 * r + 2]) for r in range(reps)]))
+        n_sel = (int(dcnt[0].item()) - N) // 3
+        assert int(dcnt[1].item()) == 0
+        sel_bytes = 13.0 * N                     # weight twice (sum, test), u, flag
+        sub_bytes = 1.0 * N + n_sel * (4 * (9 + 2 + NSH) + 4 * (4 * 9 + 3 * (2 + NSH)))
+        res["densify"] = {
+            "workload": f"{N} triangles, SH degree {cfg.sh_degree}, k = 0.1 N by inverse sigma",
+            "selected": n_sel, "select_ms": round(sel_ms, 4), "subdivide_ms": round(sub_ms, 4),
+            "select_GBps_algorithmic": round(sel_bytes / (sel_ms * 1e-3) / 1e9, 1),
+            "subdivide_GBps_algorithmic": round(sub_bytes / (sub_ms * 1e-3) / 1e9, 1),
+            "bytes_note": "select: 13 B per triangle; subdivide: 1 B per triangle + per selected "
+                          "the parent row read (236 B at SH-3) and 4 vertex rows + 3 attribute "
+                          "rows written (744 B)"}
+        del dv, do_, ds, dsh, u, sel, dws
     if not args.no_other_view:
         ov = 1 - args.view if args.view in (0, 1) else 1
         cam2 = wl.cameras[ov]

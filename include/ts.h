@@ -77,6 +77,21 @@ typedef struct ts_camera {
     int32_t width, height;
 } ts_camera;
 
+/* Window functions (Sec. 3.1).  With phi the 2D signed distance (max over
+ * the three edge lines, pixels, negative inside) and s the incentre:
+ *   TS_WINDOW_PAPER    I = ReLU(phi(p)/phi(s))^sigma                 (Eq. 1)
+ *   TS_WINDOW_SIGMOID  I = sigmoid(-phi(p)/sigma); needs o > alpha_min;
+ *                      support = the triangle grown or shrunk by
+ *                      sigma ln(o/alpha_min - 1) px (whole image when
+ *                      alpha_min = 0)                                  (Eq. 2)
+ *   TS_WINDOW_LSE      Eq. 1 with phi replaced by log sum_k exp L_k(p),
+ *                      L_k the signed distance to edge k; triangles with
+ *                      inradius <= ln 3 px have no inside and are culled
+ * The last two are the alternatives the paper discusses and sets aside. */
+#define TS_WINDOW_PAPER 0
+#define TS_WINDOW_SIGMOID 1
+#define TS_WINDOW_LSE 2
+
 /* Rasterizer constants: alpha_min is the paper's tau_cutoff. */
 typedef struct ts_config {
     float alpha_min;   /* cut-off: fragments with alpha < alpha_min are skipped (1/255) */
@@ -86,6 +101,7 @@ typedef struct ts_config {
     float r_min;       /* smallest 2D inradius kept, pixels (1e-6) */
     int32_t sh_degree; /* 0..3 */
     float bg[3];       /* background colour */
+    int32_t window;    /* TS_WINDOW_* (0: the paper's window) */
 } ts_config;
 
 /* Per-view projection state, N entries each, allocated by the caller.
@@ -298,6 +314,108 @@ const char* ts_error_string(int code);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* ts_last_error(void);
+
+/*
+ * Densification (Sec. 3.2, "Densification"; Supp.): the sampling step and
+ * the midpoint subdivision that runs between renders during training.
+ *
+ * ts_densify_select: Bernoulli sampling.  With w_i = o_i (mode
+ * TS_DENSIFY_OPACITY) or 1/sigma_i (TS_DENSIFY_INV_SIGMA; the paper
+ * alternates the two from step to step), triangle i is selected iff
+ *     u[i] < p_i = min(1, k_expected w_i / sum_j w_j),
+ * so k_expected triangles are selected on average.  u[N] holds uniform
+ * numbers in [0, 1) supplied by the caller (the library draws none).  The
+ * sum is FP64 in a fixed order (reproducible); p_i and the test are FP64.
+ *   o, sigma, u  device [N] float;  sel  device [N] bytes, 1 = selected
+ *   ws           device workspace of ts_densify_workspace_bytes(N) bytes
+ * TS_EINVAL for N < 0, a null pointer, mode out of range, or k_expected
+ * negative or not finite; TS_EWORKSPACE when ws_bytes is too small.
+ *
+ * ts_densify_subdivide: midpoint subdivision of the selected triangles, in
+ * place.  Each selected triangle (v0, v1, v2) becomes four, joining the
+ * edge midpoints m01, m12, m20 (computed as (a + b) * 0.5 in FP32): the
+ * centre child (m01, m12, m20) replaces it at its index and the corner
+ * children (v0, m01, m20), (m01, v1, m12), (m20, m12, v2) are written at
+ * N + 3r, N + 3r + 1, N + 3r + 2, r the number of selected triangles before
+ * it; the corner children copy its opacity, sigma and SH row.
+ *   v [capacity][3][3], o, sigma [capacity], sh [capacity][(deg+1)^2][3]:
+ *                device, the first N entries the current soup
+ *   sel          device [N] bytes (e.g. from ts_densify_select)
+ *   d_count      device [2] uint32: [0] = N + 3 n_selected, [1] = 1 when that
+ *                exceeds capacity, in which case nothing is written
+ *   h_count      host [2] or NULL: with it the call waits for the stream,
+ *                copies d_count and returns TS_ECAPACITY on overflow
+ * The triangles of the other per-triangle arrays a caller keeps (optimizer
+ * moments, for instance) are not moved: it handles them from sel and
+ * d_count.
+ */
+#define TS_DENSIFY_OPACITY 0
+#define TS_DENSIFY_INV_SIGMA 1
+
+size_t ts_densify_workspace_bytes(int64_t N);
+
+int ts_densify_select(const float* o, const float* sigma, int64_t N, int mode, double k_expected,
+                      const float* u, uint8_t* sel, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+int ts_densify_subdivide(float* v, float* o, float* sigma, float* sh, int sh_degree, int64_t N,
+                         int64_t capacity, const uint8_t* sel, void* ws, size_t ws_bytes,
+                         uint32_t* d_count, uint32_t* h_count, hipStream_t stream);
+
+/*
+ * One training step around the renderer (Sec. 3.3, "Optimization"; the
+ * loss terms the paper takes from the works it cites, and the learning
+ * rates of its hyperparameter table).
+ *
+ * ts_image_loss: the photometric loss (1 - lambda) L1 + lambda (1 - SSIM)
+ * of a rendered image against a target, and its gradient.  L1 is the mean
+ * |rgb - target| over the 3 H W values; SSIM is computed per channel with an
+ * 11x11 Gaussian window (standard deviation 1.5, weights summing to 1),
+ * C1 = 0.01^2, C2 = 0.03^2, pixels outside the image counting as zero, and
+ * averaged over the 3 H W values.
+ *   rgb, target  device [3][H][W] float
+ *   dL_drgb      device [3][H][W] float, overwritten with dL/drgb
+ *   loss         device [2] float or NULL: mean |rgb - target|, mean SSIM
+ *   ws           device workspace of ts_image_loss_workspace_bytes(W, H)
+ * TS_EINVAL for a non-positive size, lambda outside [0, 1] or a null
+ * pointer; TS_EWORKSPACE when ws_bytes is too small.
+ *
+ * ts_optimizer_step: adds the opacity loss beta_o mean(o) and the size loss
+ * beta_s mean(2 / |(v1 - v0) x (v2 - v0)|) to the renderer's gradients,
+ * chains them to the raw parameters (o = sigmoid(a), sigma = exp(b)) and
+ * applies one bias-corrected Adam step to v, a, b and sh; o and sigma are
+ * rewritten from the new a and b for the next render.
+ *   v [N][3][3], a, b [N], sh [N][(deg+1)^2][3]: raw parameters (device)
+ *   o, sigma [N]: their activated copies (read, then rewritten)
+ *   gv, go, gsigma, gsh: the renderer's gradients w.r.t. v, o, sigma, sh
+ *                (as ts_render_backward writes them); go and gsigma are
+ *                overwritten with the gradients w.r.t. a and b
+ *   state: the first and second moment arrays, shaped like the parameters,
+ *                zero before the first step
+ *   opt: learning rates, Adam constants, loss weights and the step number
+ *                t >= 1 (bias correction 1 - beta^t)
+ * Degree-0 SH coefficients use lr_sh_dc, the others lr_sh_rest.
+ * TS_EINVAL for N < 0, a bad degree or step, or a null pointer.
+ */
+typedef struct ts_adam_state {
+    float *m_v, *s_v, *m_a, *s_a, *m_b, *s_b, *m_sh, *s_sh;
+} ts_adam_state;
+
+typedef struct ts_optimizer {
+    float lr_v, lr_opacity, lr_sigma, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    float beta_opacity, beta_size;   /* weights of the opacity and size losses */
+    int32_t step;                    /* t >= 1 */
+} ts_optimizer;
+
+size_t ts_image_loss_workspace_bytes(int width, int height);
+
+int ts_image_loss(const float* rgb, const float* target, int width, int height, float lambda,
+                  float* dL_drgb, float* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+
+int ts_optimizer_step(float* v, float* a, float* b, float* sh, float* o, float* sigma,
+                      int sh_degree, int64_t N, float* gv, float* go, float* gsigma, float* gsh,
+                      const ts_adam_state* state, const ts_optimizer* opt, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -80,11 +80,10 @@ def subdivide(v, o, sigma, sh, sel):
     out_o = np.concatenate([o, np.zeros(3 * n, np.asarray(o).dtype)])
     out_s = np.concatenate([sigma, np.zeros(3 * n, np.asarray(sigma).dtype)])
     out_sh = np.concatenate([sh, np.zeros((3 * n,) + np.asarray(sh).shape[1:], np.asarray(sh).dtype)])
-    for r, i in enumerate(idx):
-        ch = midpoint_children(v[i])
-        out_v[i] = ch[0]
-        for c in range(3):
-            j = N + 3 * r + c
-            out_v[j] = ch[1 + c]
-            out_o[j], out_s[j], out_sh[j] = o[i], sigma[i], sh[i]
+    ch = midpoint_children(v[idx])            # [n, 4, 3, 3]
+    out_v[idx] = ch[:, 0]
+    for c in range(3):                         # corner c of the r-th selected: N + 3 r + c
+        j = N + 3 * np.arange(n) + c
+        out_v[j] = ch[:, 1 + c]
+        out_o[j], out_s[j], out_sh[j] = np.asarray(o)[idx], np.asarray(sigma)[idx], np.asarray(sh)[idx]
     return out_v, out_o, out_s, out_sh

@@ -22,12 +22,19 @@ TS_EHIP = 4
 TS_TILE = 16
 TS_G2D_STRIDE = 16
 TS_CGRAD_STRIDE = 12
+TS_WINDOW_PAPER = 0
+TS_WINDOW_SIGMOID = 1
+TS_WINDOW_LSE = 2
+TS_DENSIFY_OPACITY = 0
+TS_DENSIFY_INV_SIGMA = 1
 
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
            "ts_bin_sort", "ts_render_forward", "ts_render_forward_stats",
            "ts_prune_count_views", "ts_render_backward", "ts_raster_backward",
            "ts_project_backward", "ts_batch_layout", "ts_batch_workspace_bytes",
-           "ts_render_forward_batched", "ts_error_string", "ts_last_error")
+           "ts_render_forward_batched", "ts_densify_workspace_bytes", "ts_densify_select",
+           "ts_densify_subdivide", "ts_image_loss_workspace_bytes", "ts_image_loss",
+           "ts_optimizer_step", "ts_error_string", "ts_last_error")
 
 
 class TSError(RuntimeError):
@@ -45,7 +52,8 @@ class ts_camera(ctypes.Structure):
 class ts_config(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("z_near", ctypes.c_float), ("r_min", ctypes.c_float),
-                ("sh_degree", ctypes.c_int32), ("bg", ctypes.c_float * 3)]
+                ("sh_degree", ctypes.c_int32), ("bg", ctypes.c_float * 3),
+                ("window", ctypes.c_int32)]
 
 
 class ts_proj(ctypes.Structure):
@@ -63,6 +71,18 @@ class ts_bins(ctypes.Structure):
 
 class ts_prune_stats(ctypes.Structure):
     _fields_ = [("max_weight", ctypes.c_void_p), ("pixels", ctypes.c_void_p)]
+
+
+class ts_adam_state(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("m_v", "s_v", "m_a", "s_a", "m_b", "s_b", "m_sh",
+                                               "s_sh")]
+
+
+class ts_optimizer(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("lr_v", "lr_opacity", "lr_sigma", "lr_sh_dc",
+                                              "lr_sh_rest", "beta1", "beta2", "eps",
+                                              "beta_opacity", "beta_size")] + \
+               [("step", ctypes.c_int32)]
 
 
 class ts_view(ctypes.Structure):
@@ -115,6 +135,23 @@ def load():
     L.ts_render_forward_batched.restype = ctypes.c_int
     L.ts_render_forward_batched.argtypes = [P, P, P, P, I64, P, P, ctypes.c_int32, ctypes.c_uint32,
                                             PG, PP, PB, P, ctypes.c_size_t, P, P, P, P]
+    L.ts_densify_workspace_bytes.restype = ctypes.c_size_t
+    L.ts_densify_workspace_bytes.argtypes = [I64]
+    L.ts_densify_select.restype = ctypes.c_int
+    L.ts_densify_select.argtypes = [P, P, I64, ctypes.c_int, ctypes.c_double, P, P, P,
+                                    ctypes.c_size_t, P]
+    L.ts_densify_subdivide.restype = ctypes.c_int
+    L.ts_densify_subdivide.argtypes = [P, P, P, P, ctypes.c_int, I64, I64, P, P, ctypes.c_size_t,
+                                       P, P, P]
+    L.ts_image_loss_workspace_bytes.restype = ctypes.c_size_t
+    L.ts_image_loss_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.ts_image_loss.restype = ctypes.c_int
+    L.ts_image_loss.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_float, P, P, P,
+                                ctypes.c_size_t, P]
+    L.ts_optimizer_step.restype = ctypes.c_int
+    L.ts_optimizer_step.argtypes = [P, P, P, P, P, P, ctypes.c_int, I64, P, P, P, P,
+                                    ctypes.POINTER(ts_adam_state), ctypes.POINTER(ts_optimizer),
+                                    P]
     L.ts_error_string.restype = ctypes.c_char_p
     L.ts_error_string.argtypes = [ctypes.c_int]
     L.ts_last_error.restype = ctypes.c_char_p
@@ -269,4 +306,43 @@ def make_config(cfg) -> ts_config:
     g.z_near, g.r_min = float(cfg.z_near), float(cfg.r_min)
     g.sh_degree = int(cfg.sh_degree)
     g.bg[:] = [float(b) for b in cfg.bg]
+    g.window = int(getattr(cfg, "window", TS_WINDOW_PAPER))
     return g
+
+
+def ts_densify_workspace_bytes(N: int) -> int:
+    return int(load().ts_densify_workspace_bytes(N))
+
+
+def ts_densify_select(o, sigma, N: int, mode: int, k_expected: float, u, sel, ws, ws_bytes: int,
+                      stream: int = 0):
+    _check(load().ts_densify_select(_ptr(o), _ptr(sigma), N, mode, float(k_expected), _ptr(u),
+                                    _ptr(sel), _ptr(ws), ws_bytes, stream), "ts_densify_select")
+
+
+def ts_densify_subdivide(v, o, sigma, sh, sh_degree: int, N: int, capacity: int, sel, ws,
+                         ws_bytes: int, d_count, h_count=None, stream: int = 0):
+    """h_count: None (no host sync) or a ctypes uint32 array of 2."""
+    hc = None if h_count is None else ctypes.cast(h_count, ctypes.c_void_p)
+    _check(load().ts_densify_subdivide(_ptr(v), _ptr(o), _ptr(sigma), _ptr(sh), sh_degree, N,
+                                       capacity, _ptr(sel), _ptr(ws), ws_bytes, _ptr(d_count), hc,
+                                       stream), "ts_densify_subdivide")
+
+
+def ts_image_loss_workspace_bytes(width: int, height: int) -> int:
+    return int(load().ts_image_loss_workspace_bytes(width, height))
+
+
+def ts_image_loss(rgb, target, width: int, height: int, lam: float, dL_drgb, loss, ws,
+                  ws_bytes: int, stream: int = 0):
+    _check(load().ts_image_loss(_ptr(rgb), _ptr(target), width, height, float(lam),
+                                _ptr(dL_drgb), _ptr(loss), _ptr(ws), ws_bytes, stream),
+           "ts_image_loss")
+
+
+def ts_optimizer_step(v, a, b, sh, o, sigma, sh_degree: int, N: int, gv, go, gsigma, gsh,
+                      state: ts_adam_state, opt: ts_optimizer, stream: int = 0):
+    _check(load().ts_optimizer_step(_ptr(v), _ptr(a), _ptr(b), _ptr(sh), _ptr(o), _ptr(sigma),
+                                    sh_degree, N, _ptr(gv), _ptr(go), _ptr(gsigma), _ptr(gsh),
+                                    ctypes.byref(state), ctypes.byref(opt), stream),
+           "ts_optimizer_step")

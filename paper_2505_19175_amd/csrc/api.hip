@@ -1,5 +1,6 @@
 // api.hip -- extern "C" entry points of libts.so: argument checks, workspace
 // carve-up and kernel launches.  No allocation happens here.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -34,7 +35,7 @@ bool cfg_ok(const ts_config* g)
 {
     return g && g->sh_degree >= 0 && g->sh_degree <= TS_MAX_SH_DEGREE && g->alpha_max > 0.f &&
            g->alpha_max <= 1.f && g->alpha_min >= 0.f && g->alpha_min < g->alpha_max &&
-           g->T_min >= 0.f;
+           g->T_min >= 0.f && g->window >= TS_WINDOW_PAPER && g->window <= TS_WINDOW_LSE;
 }
 
 ts::Cam to_cam(const ts_camera* c)
@@ -53,6 +54,7 @@ ts::Cfg to_cfg(const ts_config* g)
     k.alpha_min = g->alpha_min; k.alpha_max = g->alpha_max; k.T_min = g->T_min;
     k.z_near = g->z_near; k.r_min = g->r_min; k.deg = g->sh_degree;
     k.bg[0] = g->bg[0]; k.bg[1] = g->bg[1]; k.bg[2] = g->bg[2];
+    k.window = g->window;
     return k;
 }
 
@@ -355,5 +357,102 @@ const char* ts_error_string(int code)
 }
 
 const char* ts_last_error(void) { return g_msg; }
+
+size_t ts_image_loss_workspace_bytes(int width, int height)
+{
+    return width > 0 && height > 0 ? ts::image_loss_workspace_bytes(width, height) : 0;
+}
+
+int ts_image_loss(const float* rgb, const float* target, int width, int height, float lambda,
+                  float* dL_drgb, float* loss, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (width <= 0 || height <= 0 || width > TS_MAX_IMAGE_DIM || height > TS_MAX_IMAGE_DIM ||
+        !(lambda >= 0.f && lambda <= 1.f))
+        return fail(TS_EINVAL, "ts_image_loss: bad size or lambda");
+    if (!rgb || !target || !dL_drgb || !ws) return fail(TS_EINVAL, "ts_image_loss: null pointer");
+    if (ws_bytes < ts::image_loss_workspace_bytes(width, height))
+        return fail(TS_EWORKSPACE, "ts_image_loss: workspace too small");
+    ts::launch_image_loss(rgb, target, width, height, lambda, dL_drgb, loss, ws, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_image_loss");
+}
+
+int ts_optimizer_step(float* v, float* a, float* b, float* sh, float* o, float* sigma,
+                      int sh_degree, int64_t N, float* gv, float* go, float* gsigma, float* gsh,
+                      const ts_adam_state* st, const ts_optimizer* opt, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || sh_degree < 0 || sh_degree > TS_MAX_SH_DEGREE || !opt || opt->step < 1 || !st)
+        return fail(TS_EINVAL, "ts_optimizer_step: bad size, degree, step or null settings");
+    if (N == 0) return TS_OK;
+    if (!v || !a || !b || !sh || !o || !sigma || !gv || !go || !gsigma || !gsh || !st->m_v ||
+        !st->s_v || !st->m_a || !st->s_a || !st->m_b || !st->s_b || !st->m_sh || !st->s_sh)
+        return fail(TS_EINVAL, "ts_optimizer_step: null pointer");
+    ts::launch_train_reg(v, o, sigma, N, opt->beta_opacity, opt->beta_size, gv, go, gsigma, stream);
+    const float bc1 = (float)(1.0 - pow((double)opt->beta1, opt->step));
+    const float bc2 = (float)(1.0 - pow((double)opt->beta2, opt->step));
+    const int K3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+    ts::launch_adam(v, gv, st->m_v, st->s_v, 9 * N, 9, 9, opt->lr_v, opt->lr_v, opt->beta1,
+                    opt->beta2, bc1, bc2, opt->eps, 0, nullptr, stream);
+    ts::launch_adam(a, go, st->m_a, st->s_a, N, 1, 1, opt->lr_opacity, opt->lr_opacity,
+                    opt->beta1, opt->beta2, bc1, bc2, opt->eps, 1, o, stream);
+    ts::launch_adam(b, gsigma, st->m_b, st->s_b, N, 1, 1, opt->lr_sigma, opt->lr_sigma,
+                    opt->beta1, opt->beta2, bc1, bc2, opt->eps, 2, sigma, stream);
+    ts::launch_adam(sh, gsh, st->m_sh, st->s_sh, (int64_t)K3 * N, K3, 3, opt->lr_sh_dc,
+                    opt->lr_sh_rest, opt->beta1, opt->beta2, bc1, bc2, opt->eps, 0, nullptr,
+                    stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_optimizer_step");
+}
+
+size_t ts_densify_workspace_bytes(int64_t N) { return ts::densify_workspace_bytes(N < 0 ? 0 : N); }
+
+int ts_densify_select(const float* o, const float* sigma, int64_t N, int mode, double k_expected,
+                      const float* u, uint8_t* sel, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || N > 0xffffffffll || (mode != TS_DENSIFY_OPACITY && mode != TS_DENSIFY_INV_SIGMA) ||
+        !(k_expected >= 0.0) || k_expected > 1e300)
+        return fail(TS_EINVAL, "ts_densify_select: bad size, mode or expected count");
+    if (N == 0) return TS_OK;
+    if (!o || !sigma || !u || !sel || !ws) return fail(TS_EINVAL, "ts_densify_select: null pointer");
+    if (ws_bytes < ts::densify_workspace_bytes(N))
+        return fail(TS_EWORKSPACE, "ts_densify_select: workspace too small");
+    ts::launch_densify_select(o, sigma, N, mode, k_expected, u, sel, ws, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_densify_select");
+}
+
+int ts_densify_subdivide(float* v, float* o, float* sigma, float* sh, int sh_degree, int64_t N,
+                         int64_t capacity, const uint8_t* sel, void* ws, size_t ws_bytes,
+                         uint32_t* d_count, uint32_t* h_count, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || capacity < N || capacity > 0xffffffffll || sh_degree < 0 ||
+        sh_degree > TS_MAX_SH_DEGREE)
+        return fail(TS_EINVAL, "ts_densify_subdivide: bad size, capacity or degree");
+    if (!d_count || (N > 0 && (!v || !o || !sigma || !sh || !sel || !ws)))
+        return fail(TS_EINVAL, "ts_densify_subdivide: null pointer");
+    if (N > 0 && ws_bytes < ts::densify_workspace_bytes(N))
+        return fail(TS_EWORKSPACE, "ts_densify_subdivide: workspace too small");
+    if (N == 0) {
+        ts::launch_fill_u32(d_count, 1, 0u, stream);
+        ts::launch_fill_u32(d_count + 1, 1, 0u, stream);
+    } else {
+        const int nsh = 3 * (sh_degree + 1) * (sh_degree + 1);
+        ts::launch_densify_subdivide(v, o, sigma, sh, nsh, N, capacity, sel, ws, d_count, stream);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ts_densify_subdivide");
+    if (h_count) {
+        e = hipMemcpyAsync(h_count, d_count, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "ts_densify_subdivide");
+        if (h_count[1] != 0u)
+            return fail(TS_ECAPACITY, "ts_densify_subdivide: subdivided soup exceeds capacity");
+    }
+    return TS_OK;
+}
 
 }  // extern "C"

@@ -23,12 +23,13 @@ __device__ __forceinline__ void block_store(float* __restrict__ dst, const float
 // camera space -> world vertices; colour -> SH coefficients and view
 // direction.  Consumes g2d (re-zeroes it).
 // g2d slots: 0-2 dL/dA_k, 3-5 dL/dB_k, 6-8 dL/dC_k, 9 dL/do, 10 dL/dsigma,
-//            11-13 dL/drgb, 14 dL/dz.
+//            11-13 dL/drgb, 14 dL/dz, 15 dL/dr (LogSumExp window: the
+//            inradius through phi_lse(s) = ln 3 - r).
 // A block handles 256 consecutive triangles and writes their gradient rows
 // through LDS, so every store of the block is contiguous (the SH gradient is
 // the largest array the step writes: 12 (deg+1)^2 bytes per triangle).
 // ---------------------------------------------------------------------------
-template <int DEG>
+template <int DEG, int WIN>
 __global__ __launch_bounds__(256) void k_backproject(
     const float* __restrict__ v, const float4* __restrict__ cgrad, int64_t N, Cam cam, Cfg cfg,
     const short4* __restrict__ rect, const uint32_t* __restrict__ ntiles,
@@ -73,13 +74,15 @@ __global__ __launch_bounds__(256) void k_backproject(
         const short4 rc = rect[i];
         const double ax = (double)rc.x, ay = (double)rc.z;
 
-        // coefficients -> (w_k, e_k, q_k)
+        // coefficients -> (w_k, e_k, q_k); w_k = P / (S l_k) for Eq. 1,
+        // sgn(S) / l_k for the distance form of the alternatives
         double gq[3][2] = {{0, 0}, {0, 0}, {0, 0}};
         double ge[3][2];
         double gP = 0.0, gS = 0.0, gl[3];
+        const double sgn = g.S > 0.0 ? 1.0 : -1.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double w = g.P / (g.S * g.len[k]);
+            const double w = WIN == TS_WINDOW_PAPER ? g.P / (g.S * g.len[k]) : sgn / g.len[k];
             const double qx = g.q[k][0] - ax, qy = g.q[k][1] - ay;
             const double ex = g.e[k][0], ey = g.e[k][1];
             const double gA = G[k], gB = G[3 + k], gC = G[6 + k];
@@ -89,10 +92,16 @@ __global__ __launch_bounds__(256) void k_backproject(
             ge[k][1] = -gA * w - gC * w * (0.5 - qx);
             gq[k][0] += gC * w * ey;
             gq[k][1] += -gC * w * ex;
-            // w = P / (S l_k)
-            gP += gw / (g.S * g.len[k]);
-            gS += -gw * w / g.S;
+            if constexpr (WIN == TS_WINDOW_PAPER) {   // w = P / (S l_k)
+                gP += gw / (g.S * g.len[k]);
+                gS += -gw * w / g.S;
+            }
             gl[k] = -gw * w / g.len[k];
+        }
+        if constexpr (WIN == TS_WINDOW_LSE) {   // r = |S| / P
+            const double gr = (double)G[15];
+            gS += gr * sgn / g.P;
+            gP += -gr * (fabs(g.S) / g.P) / g.P;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -199,20 +208,26 @@ __global__ __launch_bounds__(256) void k_backproject(
     }
 }
 
+template <int DEG, int WIN>
+struct BackprojectLaunch {
+    static void run(dim3 grid, hipStream_t stream, const float* v, const float4* cg, int64_t N,
+                    const Cam& cam, const Cfg& cfg, const short4* r4, const uint32_t* ntiles,
+                    float4* g4, float* gv, float* go, float* gsig, float* gsh)
+    {
+        hipLaunchKernelGGL((k_backproject<DEG, WIN>), grid, dim3(256), 0, stream, v, cg, N, cam,
+                           cfg, r4, ntiles, g4, gv, go, gsig, gsh);
+    }
+};
+
 void launch_backproject(const float* v, const float* cgrad, int64_t N, const Cam& cam,
                         const Cfg& cfg, const int16_t* rect, const uint32_t* ntiles, float* g2d,
                         float* gv, float* go, float* gsig, float* gsh, hipStream_t stream)
 {
-    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
-    const short4* r4 = reinterpret_cast<const short4*>(rect);
-    float4* g4 = reinterpret_cast<float4*>(g2d);
-    const float4* cg = reinterpret_cast<const float4*>(cgrad);
-    switch (cfg.deg) {
-    case 0: hipLaunchKernelGGL(k_backproject<0>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
-    case 1: hipLaunchKernelGGL(k_backproject<1>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
-    case 2: hipLaunchKernelGGL(k_backproject<2>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
-    default: hipLaunchKernelGGL(k_backproject<3>, grid, block, 0, stream, v, cg, N, cam, cfg, r4, ntiles, g4, gv, go, gsig, gsh); break;
-    }
+    const dim3 grid((unsigned)((N + 255) / 256));
+    dispatch_deg_win<BackprojectLaunch>(cfg.deg, cfg.window, grid, stream, v,
+                                        reinterpret_cast<const float4*>(cgrad), N, cam, cfg,
+                                        reinterpret_cast<const short4*>(rect), ntiles,
+                                        reinterpret_cast<float4*>(g2d), gv, go, gsig, gsh);
 }
 
 }  // namespace ts

@@ -13,7 +13,8 @@ namespace ts {
 // Set up triangle `tri` for one camera and write entry `e` of the outputs
 // (e = tri for a single view, view * N + tri in a batch).  The SH
 // coefficients are loaded on first use into c (shared across views).
-template <int DEG>
+// WIN is the window function (TS_WINDOW_*).
+template <int DEG, int WIN>
 __device__ __forceinline__ void project_one(const float vv[9], float oi, float si,
                                             const float* __restrict__ sh, int64_t tri,
                                             float* c, bool& c_loaded, const Cam& cam,
@@ -28,7 +29,9 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
     depth[e] = (float)zc;
 
     const double r = g.P > 0.0 ? fabs(g.S) / g.P : 0.0;
-    bool vis = g.front && (r >= (double)cfg.r_min) && (oi >= cfg.alpha_min) && (si > 0.f);
+    // the sigmoid stays below 1, so it needs o > alpha_min strictly
+    const bool o_ok = WIN == TS_WINDOW_SIGMOID ? oi > cfg.alpha_min : oi >= cfg.alpha_min;
+    bool vis = g.front && (r >= (double)cfg.r_min) && o_ok && (si > 0.f);
     if (vis && !c_loaded) {
         // Issue the SH row loads before the costly tight-box set-up, so they are
         // in flight during it, for triangles whose full box holds a pixel
@@ -46,15 +49,41 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
         }
     }
 
-    // Tight region {o I >= alpha_min} = {u >= u_min}: the triangle scaled
-    // about its incentre by 1 - u_min, u_min = (alpha_min/o)^(1/sigma).
+    // Tight region {o I >= alpha_min} = {u_k >= u_min for every k}: the
+    // triangle scaled about its incentre by f = 1 - u_min / u(s), u(s) = 1
+    // for Eq. 1 and r for the distance form.
+    //   Eq. 1:    u_min = (alpha_min/o)^(1/sigma)
+    //   sigmoid:  o sigmoid(d/sigma) >= alpha_min  <=>  d >= -sigma ln(o/alpha_min - 1)
+    //             (negative: the region reaches past the triangle); nothing
+    //             is left when that bound reaches r, everything when
+    //             alpha_min = 0
+    //   LSE:      phi_lse >= phi_max, so the region lies in {phi_max <=
+    //             u_min phi_lse(s)}: a distance bound of u_min (r - ln 3)
     int px0 = 0, px1 = -1, py0 = 0, py1 = -1;
-    double umin = 0.0;
+    double umin = 0.0, phis = 0.0;
+    bool whole = false;   // unbounded support: the whole image
     if (vis) {
         const double sx = (g.len[1] * g.q[0][0] + g.len[2] * g.q[1][0] + g.len[0] * g.q[2][0]) / g.P;
         const double sy = (g.len[1] * g.q[0][1] + g.len[2] * g.q[1][1] + g.len[0] * g.q[2][1]) / g.P;
-        umin = pow((double)cfg.alpha_min / (double)oi, 1.0 / (double)si);
-        const double f = 1.0 - umin;
+        double f;
+        if constexpr (WIN == TS_WINDOW_SIGMOID) {
+            if (cfg.alpha_min > 0.f) {
+                umin = -(double)si * log((double)oi / (double)cfg.alpha_min - 1.0);
+                vis = umin < r;
+            } else {
+                whole = true;
+                umin = -INFINITY;
+            }
+            f = whole ? 1.0 : 1.0 - umin / r;
+        } else if constexpr (WIN == TS_WINDOW_LSE) {
+            phis = kLn3 - r;
+            vis = phis < 0.0;
+            umin = pow((double)cfg.alpha_min / (double)oi, 1.0 / (double)si) * (r - kLn3);
+            f = 1.0 - umin / r;
+        } else {
+            umin = pow((double)cfg.alpha_min / (double)oi, 1.0 / (double)si);
+            f = 1.0 - umin;
+        }
         double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -63,11 +92,15 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
             xmin = fmin(xmin, x); xmax = fmax(xmax, x);
             ymin = fmin(ymin, y); ymax = fmax(ymax, y);
         }
+        if (whole) {
+            xmin = ymin = -1e300;
+            xmax = ymax = 1e300;
+        }
         const double fx0 = fmax(0.0, ceil(xmin - 0.5));
         const double fx1 = fmin((double)(cam.W - 1), floor(xmax - 0.5));
         const double fy0 = fmax(0.0, ceil(ymin - 0.5));
         const double fy1 = fmin((double)(cam.H - 1), floor(ymax - 0.5));
-        if (fx0 <= fx1 && fy0 <= fy1) {   // false for NaN as well
+        if (vis && fx0 <= fx1 && fy0 <= fy1) {   // false for NaN as well
             px0 = (int)fx0; px1 = (int)fx1; py0 = (int)fy0; py1 = (int)fy1;
         } else {
             vis = false;
@@ -82,11 +115,13 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
     ntiles[e] = (uint32_t)((px1 / kTile - px0 / kTile + 1) * (py1 / kTile - py0 / kTile + 1));
 
     TriRecord R;
-    // u_k(p) = w_k cross(e_k, p - q_k), w_k = P / (2A l_k), relative to the anchor
+    // u_k(p) = w_k cross(e_k, p - q_k), w_k = P / (2A l_k) (Eq. 1) or
+    // sgn(2A) / l_k (distance form), relative to the anchor
     const double ax = (double)px0, ay = (double)py0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double w = g.P / (g.S * g.len[k]);
+        const double w = WIN == TS_WINDOW_PAPER ? g.P / (g.S * g.len[k])
+                                                : (g.S > 0.0 ? 1.0 : -1.0) / g.len[k];
         const double qx = g.q[k][0] - ax, qy = g.q[k][1] - ay;
         R.A[k] = -w * g.e[k][1];
         R.B[k] = w * g.e[k][0];
@@ -101,9 +136,16 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
     R.tri = (uint32_t)tri;
     // A pixel with u below u_min (1 - 2^-10) cannot reach alpha_min through the
     // FP32 window (its error is orders of magnitude below that margin);
-    // rounded toward zero so the bound stays below u_min.
-    R.ut = __double2float_rz(umin * (1.0 - 1.0 / 1024.0));
-    R.pad[0] = R.pad[1] = R.pad[2] = 0.f;
+    // rounded toward zero so the bound stays below u_min.  The sigmoid's
+    // bound can be near zero or negative: it keeps a margin of
+    // (|u_min| + sigma) 2^-10 pixels, rounded down.
+    if constexpr (WIN == TS_WINDOW_SIGMOID)
+        R.ut = whole ? -INFINITY
+                     : __double2float_rd(umin - (fabs(umin) + (double)si) * (1.0 / 1024.0));
+    else
+        R.ut = __double2float_rz(umin * (1.0 - 1.0 / 1024.0));
+    R.phis = (float)phis;
+    R.pad[0] = R.pad[1] = 0.f;
 
     // colour: real SH along the view direction, + 1/2, clamped at zero
     double d[3], nrm;
@@ -150,7 +192,7 @@ __device__ __forceinline__ void project_one(const float vv[9], float oi, float s
     }
 }
 
-template <int DEG>
+template <int DEG, int WIN>
 __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ v, const float* __restrict__ o, const float* __restrict__ sigma,
     const float* __restrict__ sh, int64_t N, Cam cam, Cfg cfg, TriRecord* __restrict__ rec,
@@ -162,13 +204,13 @@ __global__ __launch_bounds__(256) void k_project(
     float vv[9], c[3 * (DEG + 1) * (DEG + 1)];
     bool c_loaded = false;
     load_vertices(v, i, vv);
-    project_one<DEG>(vv, o[i], sigma[i], sh, i, c, c_loaded, cam, cfg, i, rec, rect, depth,
-                     ntiles, cgrad);
+    project_one<DEG, WIN>(vv, o[i], sigma[i], sh, i, c, c_loaded, cam, cfg, i, rec, rect, depth,
+                          ntiles, cgrad);
 }
 
 // All views of a batch: each triangle is read once (vertices, opacity,
 // sigma, and its SH row only if some view keeps it) and set up per view.
-template <int DEG>
+template <int DEG, int WIN>
 __global__ __launch_bounds__(256) void k_project_views(
     const float* __restrict__ v, const float* __restrict__ o, const float* __restrict__ sigma,
     const float* __restrict__ sh, int64_t N, const ts_view* __restrict__ views,
@@ -191,25 +233,44 @@ __global__ __launch_bounds__(256) void k_project_views(
         for (int a = 0; a < 3; ++a) cam.t[a] = vc.t[a];
         cam.fx = vc.fx; cam.fy = vc.fy; cam.cx = vc.cx; cam.cy = vc.cy;
         cam.W = vc.width; cam.H = vc.height;
-        project_one<DEG>(vv, oi, si, sh, i, c, c_loaded, cam, cfg, (int64_t)view * N + i, rec,
-                         rect, depth, ntiles, nullptr);
+        project_one<DEG, WIN>(vv, oi, si, sh, i, c, c_loaded, cam, cfg, (int64_t)view * N + i,
+                              rec, rect, depth, ntiles, nullptr);
     }
 }
+
+template <int DEG, int WIN>
+struct ProjectLaunch {
+    static void run(dim3 grid, hipStream_t stream, const float* v, const float* o,
+                    const float* sigma, const float* sh, int64_t N, const Cam& cam,
+                    const Cfg& cfg, TriRecord* r, short4* r4, float* depth, uint32_t* ntiles,
+                    float4* cg)
+    {
+        hipLaunchKernelGGL((k_project<DEG, WIN>), grid, dim3(256), 0, stream, v, o, sigma, sh, N,
+                           cam, cfg, r, r4, depth, ntiles, cg);
+    }
+};
+
+template <int DEG, int WIN>
+struct ProjectViewsLaunch {
+    static void run(dim3 grid, hipStream_t stream, const float* v, const float* o,
+                    const float* sigma, const float* sh, int64_t N, const ts_view* views,
+                    const uint32_t* ctl, const Cfg& cfg, TriRecord* r, short4* r4, float* depth,
+                    uint32_t* ntiles)
+    {
+        hipLaunchKernelGGL((k_project_views<DEG, WIN>), grid, dim3(256), 0, stream, v, o, sigma,
+                           sh, N, views, ctl, cfg, r, r4, depth, ntiles);
+    }
+};
 
 void launch_project(const float* v, const float* o, const float* sigma, const float* sh,
                     int64_t N, const Cam& cam, const Cfg& cfg, void* rec, int16_t* rect,
                     float* depth, uint32_t* ntiles, float* cgrad, hipStream_t stream)
 {
-    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
-    TriRecord* r = reinterpret_cast<TriRecord*>(rec);
-    short4* r4 = reinterpret_cast<short4*>(rect);
-    float4* cg = reinterpret_cast<float4*>(cgrad);
-    switch (cfg.deg) {
-    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, cg); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, cg); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, cg); break;
-    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, stream, v, o, sigma, sh, N, cam, cfg, r, r4, depth, ntiles, cg); break;
-    }
+    const dim3 grid((unsigned)((N + 255) / 256));
+    dispatch_deg_win<ProjectLaunch>(cfg.deg, cfg.window, grid, stream, v, o, sigma, sh, N, cam,
+                                    cfg, reinterpret_cast<TriRecord*>(rec),
+                                    reinterpret_cast<short4*>(rect), depth, ntiles,
+                                    reinterpret_cast<float4*>(cgrad));
 }
 
 void launch_project_views(const float* v, const float* o, const float* sigma, const float* sh,
@@ -217,15 +278,10 @@ void launch_project_views(const float* v, const float* o, const float* sigma, co
                           void* rec, int16_t* rect, float* depth, uint32_t* ntiles,
                           hipStream_t stream)
 {
-    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
-    TriRecord* r = reinterpret_cast<TriRecord*>(rec);
-    short4* r4 = reinterpret_cast<short4*>(rect);
-    switch (cfg.deg) {
-    case 0: hipLaunchKernelGGL(k_project_views<0>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
-    case 1: hipLaunchKernelGGL(k_project_views<1>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
-    case 2: hipLaunchKernelGGL(k_project_views<2>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
-    default: hipLaunchKernelGGL(k_project_views<3>, grid, block, 0, stream, v, o, sigma, sh, N, views, ctl, cfg, r, r4, depth, ntiles); break;
-    }
+    const dim3 grid((unsigned)((N + 255) / 256));
+    dispatch_deg_win<ProjectViewsLaunch>(cfg.deg, cfg.window, grid, stream, v, o, sigma, sh, N,
+                                         views, ctl, cfg, reinterpret_cast<TriRecord*>(rec),
+                                         reinterpret_cast<short4*>(rect), depth, ntiles);
 }
 
 }  // namespace ts

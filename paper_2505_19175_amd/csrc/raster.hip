@@ -18,7 +18,8 @@
 //
 // The window is evaluated as three FP64 affine functions per pixel (gfx950
 // issues v_fma_f64 at the rate of unpacked v_fma_f32); the rest is FP32,
-// written without branches so a wave issues one path per step.
+// written without branches so a wave issues one path per step.  Every
+// kernel is instantiated per window function (TS_WINDOW_*).
 #include "ts_device.h"
 #include "ts_kernels.h"
 
@@ -27,7 +28,21 @@ namespace ts {
 constexpr int kBatch = kBlock;   // entries staged per batch
 constexpr int kChunks = 6;       // 16-byte chunks of a record the raster reads (+ z)
 
-struct Stage {
+// phi_lse(s) of each staged entry, for the LogSumExp window only: the other
+// windows get an empty base, so their LDS footprint (32000 bytes, 25 blocks
+// of the 1280-byte allocation unit: five workgroups per CU) is unchanged.
+template <int WIN>
+struct StageExtra {
+    static constexpr bool kLse = false;
+};
+template <>
+struct StageExtra<TS_WINDOW_LSE> {
+    static constexpr bool kLse = true;
+    float ps[kBatch];
+};
+
+template <int WIN>
+struct StageT : StageExtra<WIN> {
     float4 q[kChunks][kBatch];
     float z[kBatch];
     uint16_t hit[kBatch];        // bit 4 w + g: may composite in block g of quadrant w
@@ -53,6 +68,7 @@ union RecView {
 // The staged copy holds C_k relative to the tile's corner pixel (tx0, ty0)
 // instead of the record's anchor, so a lane evaluates u_k = A_k dx + B_k dy +
 // C_k with its own fixed offset in the tile (no per-step conversion).
+template <class Stage>
 __device__ __forceinline__ void write_stage(Stage& S, RecView& u, int tx0, int ty0)
 {
     const double ox = (double)(tx0 - u.r.ax), oy = (double)(ty0 - u.r.ay);
@@ -61,18 +77,22 @@ __device__ __forceinline__ void write_stage(Stage& S, RecView& u, int tx0, int t
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = u.q[c];
     S.z[threadIdx.x] = u.r.z;
+    if constexpr (Stage::kLse) S.ps[threadIdx.x] = u.r.phis;
 }
 
+template <class Stage>
 __device__ __forceinline__ void stage_copy(Stage& S, const TriRecord* __restrict__ rec,
                                            uint32_t tri, int tx0, int ty0)
 {
     const float4* src = reinterpret_cast<const float4*>(rec + tri);
     RecView u;
+    constexpr int nc = Stage::kLse ? 8 : 7;   // phis sits in chunk 7
 #pragma unroll
-    for (int c = 0; c < 7; ++c) u.q[c] = src[c];
+    for (int c = 0; c < nc; ++c) u.q[c] = src[c];
     write_stage(S, u, tx0, ty0);
 }
 
+template <class Stage>
 __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restrict__ rec,
                                               uint32_t tri, int tx0, int ty0)
 {
@@ -128,12 +148,14 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
     return m;
 }
 
+template <class Stage>
 __device__ __forceinline__ TriRecord read_rec(const Stage& S, int j)
 {
     RecView u;
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) u.q[c] = S.q[c][j];
     u.r.z = S.z[j];
+    if constexpr (Stage::kLse) u.r.phis = S.ps[j];
     return u.r;
 }
 
@@ -144,6 +166,7 @@ struct Lens {
     int n0, n1, n2, n3;
 };
 
+template <class Stage>
 __device__ __forceinline__ Lens build_lists(Stage& S, int n, int w, int lane, int lim0,
                                             int lim1, int lim2, int lim3)
 {
@@ -182,16 +205,29 @@ __device__ __forceinline__ int per_row(int g, int j0, int j1, int j2, int j3)
 }
 
 // Window and opacity of a staged record at the pixel (dx, dy) from the
-// tile's corner; u <= 0 gives alpha = 0.  Forward and backward call exactly
-// this.
-__device__ __forceinline__ double frag_alpha(const TriRecord& r, double dx, double dy,
-                                             float alpha_max, Frag& f)
+// tile's corner.  Returns whether the pixel is in the window's support (the
+// forms of Eq. 1: u > 0; the sigmoid: everywhere).  Forward and backward
+// call exactly this.
+template <int WIN>
+__device__ __forceinline__ bool frag_alpha(const TriRecord& r, double dx, double dy,
+                                           float alpha_max, Frag& f)
 {
     int k;
-    const double u = edge_min(r.A, r.B, r.C, dx, dy, k);
-    window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
-    f.k = k;
-    return u;
+    if constexpr (WIN == TS_WINDOW_SIGMOID) {
+        const double d = edge_min(r.A, r.B, r.C, dx, dy, k);
+        sigmoid_alpha(d, r.o, r.sigma, alpha_max, f);
+        f.k = k;
+        return true;
+    } else if constexpr (WIN == TS_WINDOW_LSE) {
+        const double u = lse_u(r.A, r.B, r.C, dx, dy, (double)r.phis, f);
+        window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
+        return u > 0.0;
+    } else {
+        const double u = edge_min(r.A, r.B, r.C, dx, dy, k);
+        window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
+        f.k = k;
+        return u > 0.0;
+    }
 }
 
 struct Pix {
@@ -253,9 +289,10 @@ struct TileJob {
     uint32_t* pixels;   // and pixels where it is composited
 };
 
+template <int WIN>
 __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
                                          const uint32_t* __restrict__ vals, const Cfg& cfg,
-                                         const TileJob& J, Stage& S)
+                                         const TileJob& J, StageT<WIN>& S)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const Pix P = pixel_of(J.tx, J.ty);
@@ -294,8 +331,8 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             jn = lst[k + 1 < kBatch ? k + 1 : 0];
             const TriRecord r = read_rec(S, j);
             Frag f;
-            const double u = frag_alpha(r, dxt, dyt, cfg.alpha_max, f);
-            const bool contrib = act && u > 0.0 && f.a >= cfg.alpha_min;
+            const bool in = frag_alpha<WIN>(r, dxt, dyt, cfg.alpha_max, f);
+            const bool contrib = act && in && f.a >= cfg.alpha_min;
             const float Tn = T * (1.f - f.a);
             const bool stop = contrib && Tn < cfg.T_min;
             const bool comp = contrib && !stop;
@@ -340,6 +377,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     }
 }
 
+template <int WIN>
 __global__ __launch_bounds__(256) void k_raster_fwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
@@ -348,7 +386,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     uint16_t* __restrict__ out_blocks, float* __restrict__ max_weight,
     uint32_t* __restrict__ pixels)
 {
-    __shared__ Stage S;
+    __shared__ StageT<WIN> S;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
     TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
@@ -361,6 +399,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
 // the next tile from a queue until the batch's tiles run out.  views[] is
 // sorted by tile_offset; ctl[0] = views in the batch, ctl[1] = their tiles
 // (both already clamped to the buffers).
+template <int WIN>
 __global__ __launch_bounds__(256) void k_raster_fwd_queue(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order,
@@ -368,8 +407,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
     uint32_t* __restrict__ queue, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
     float* __restrict__ out_depth)
 {
-    __shared__ Stage S;
-    __shared__ uint32_t s_t;
+    __shared__ StageT<WIN> S;
+    // the queue slot lives in the stage's forward block-mask words: every
+    // thread reads it before fwd_tile's first barrier, and fwd_tile clears
+    // those words only after that barrier.  A separate variable would push
+    // the workgroup past 25 LDS allocation units (four per CU, not five).
+    uint32_t& s_t = S.comp[0];
     const uint32_t nviews = ctl[0], total = ctl[1];
     for (;;) {
         __syncthreads();
@@ -438,6 +481,7 @@ __device__ __forceinline__ uint32_t row_max(uint32_t x)
     return x;
 }
 
+template <int WIN>
 __global__ __launch_bounds__(256) void k_raster_bwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
@@ -446,7 +490,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
     const float* __restrict__ T_final, const uint32_t* __restrict__ last_in,
     const uint16_t* __restrict__ blocks, float* __restrict__ g2d)
 {
-    __shared__ Stage S;
+    __shared__ StageT<WIN> S;
     __shared__ uint32_t s_max;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
@@ -520,8 +564,8 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             const TriRecord r = read_rec(S, jc);
             const int dx = P.px - r.ax, dy = P.py - r.ay;   // anchor form of the coefficients
             Frag f;
-            const double u = frag_alpha(r, dxt, dyt, cfg.alpha_max, f);
-            const bool contrib = j >= 0 && inside && lo_ + (uint32_t)j < my_last && u > 0.0 &&
+            const bool in = frag_alpha<WIN>(r, dxt, dyt, cfg.alpha_max, f);
+            const bool contrib = j >= 0 && inside && lo_ + (uint32_t)j < my_last && in &&
                                  f.a >= cfg.alpha_min;
             if (__ballot(contrib) == 0ull) continue;
 
@@ -545,20 +589,48 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             const bool open = contrib && f.oI <= cfg.alpha_max;   // not clamped
             const float gI = ga * r.o;
             v[9] = open ? ga * f.I : 0.f;                                  // dL/do
-            v[10] = open ? gI * f.I * (f.lg * 0.69314718055994531f) : 0.f;  // I ln u
-            const float gu = open ? gI * r.sigma * f.I * __builtin_amdgcn_rcpf(f.u) : 0.f;
-            const float a_ = gu * (float)dx, b_ = gu * (float)dy;
-            v[0] = f.k == 0 ? a_ : 0.f;
-            v[1] = f.k == 1 ? a_ : 0.f;
-            v[2] = f.k == 2 ? a_ : 0.f;
-            v[3] = f.k == 0 ? b_ : 0.f;
-            v[4] = f.k == 1 ? b_ : 0.f;
-            v[5] = f.k == 2 ? b_ : 0.f;
-            v[6] = f.k == 0 ? gu : 0.f;
-            v[7] = f.k == 1 ? gu : 0.f;
-            v[8] = f.k == 2 ? gu : 0.f;
+            if constexpr (WIN == TS_WINDOW_LSE) {
+                // u = phi_lse / phi_lse(s): dphi_lse/dd_k = -w_k (softmax weight),
+                // du/dr = u / phi_lse(s) (phi_lse(s) = ln 3 - r) into slot 15
+                v[10] = open ? gI * f.I * (f.lg * 0.69314718055994531f) : 0.f;  // I ln u
+                const float gu = open ? gI * r.sigma * f.I * __builtin_amdgcn_rcpf(f.u) : 0.f;
+                const float rp = __builtin_amdgcn_rcpf(r.phis);
+                const float gphi = gu * rp;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const float gd = -f.w[q] * gphi;
+                    v[q] = gd * (float)dx;
+                    v[3 + q] = gd * (float)dy;
+                    v[6 + q] = gd;
+                }
+                v[15] = gu * f.u * rp;
+            } else {
+                float gu;
+                if constexpr (WIN == TS_WINDOW_SIGMOID) {
+                    // I = sigmoid(d / sigma): dI/dd = I (1 - I) / sigma,
+                    // dI/dsigma = -I (1 - I) d / sigma^2
+                    const float rs = __builtin_amdgcn_rcpf(r.sigma);
+                    const float dI = f.I * f.Ic * rs;
+                    v[10] = open ? -gI * dI * f.u * rs : 0.f;
+                    gu = open ? gI * dI : 0.f;
+                } else {
+                    v[10] = open ? gI * f.I * (f.lg * 0.69314718055994531f) : 0.f;  // I ln u
+                    gu = open ? gI * r.sigma * f.I * __builtin_amdgcn_rcpf(f.u) : 0.f;
+                }
+                const float a_ = gu * (float)dx, b_ = gu * (float)dy;
+                v[0] = f.k == 0 ? a_ : 0.f;
+                v[1] = f.k == 1 ? a_ : 0.f;
+                v[2] = f.k == 2 ? a_ : 0.f;
+                v[3] = f.k == 0 ? b_ : 0.f;
+                v[4] = f.k == 1 ? b_ : 0.f;
+                v[5] = f.k == 2 ? b_ : 0.f;
+                v[6] = f.k == 0 ? gu : 0.f;
+                v[7] = f.k == 1 ? gu : 0.f;
+                v[8] = f.k == 2 ? gu : 0.f;
+            }
             const float tot = row_reduce16(v, P.i);
-            if (j >= 0 && P.i < 15 && tot != 0.f)
+            // slot 15 carries dL/dr for the LogSumExp window only
+            if (j >= 0 && P.i < (WIN == TS_WINDOW_LSE ? 16 : 15) && tot != 0.f)
                 unsafeAtomicAdd(g2d + (int64_t)S.tri[jc] * TS_G2D_STRIDE + P.i, tot);
         }
         hi_ = lo_;
@@ -571,10 +643,17 @@ void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t
                            uint32_t* last, uint16_t* blocks, float* max_weight, uint32_t* pixels,
                            hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_raster_fwd, dim3(num_tiles), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks, max_weight,
-                       pixels);
+    const TriRecord* r = reinterpret_cast<const TriRecord*>(rec);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(num_tiles), dim3(kBlock), 0, stream, r, vals, ranges, order,
+                           cam, cfg, tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks,
+                           max_weight, pixels);
+    };
+    switch (cfg.window) {
+    case TS_WINDOW_SIGMOID: go(k_raster_fwd<TS_WINDOW_SIGMOID>); break;
+    case TS_WINDOW_LSE: go(k_raster_fwd<TS_WINDOW_LSE>); break;
+    default: go(k_raster_fwd<TS_WINDOW_PAPER>); break;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_prune_views(uint32_t* __restrict__ pixels,
@@ -599,9 +678,16 @@ void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const ui
                                  int workgroups, float* rgb, float* alpha, float* depth,
                                  hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_raster_fwd_queue, dim3(workgroups), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, views, ctl,
-                       cfg, queue, rgb, alpha, depth);
+    const TriRecord* r = reinterpret_cast<const TriRecord*>(rec);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(workgroups), dim3(kBlock), 0, stream, r, vals, ranges,
+                           order, views, ctl, cfg, queue, rgb, alpha, depth);
+    };
+    switch (cfg.window) {
+    case TS_WINDOW_SIGMOID: go(k_raster_fwd_queue<TS_WINDOW_SIGMOID>); break;
+    case TS_WINDOW_LSE: go(k_raster_fwd_queue<TS_WINDOW_LSE>); break;
+    default: go(k_raster_fwd_queue<TS_WINDOW_PAPER>); break;
+    }
 }
 
 void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
@@ -611,10 +697,17 @@ void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_
                             const uint32_t* last, const uint16_t* blocks, float* g2d,
                             hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_raster_bwd, dim3(num_tiles), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const TriRecord*>(rec), vals, ranges, order, cam, cfg,
-                       tiles_x, num_tiles, dL_drgb, dL_dalpha, dL_ddepth, T_final, last, blocks,
-                       g2d);
+    const TriRecord* r = reinterpret_cast<const TriRecord*>(rec);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(num_tiles), dim3(kBlock), 0, stream, r, vals, ranges, order,
+                           cam, cfg, tiles_x, num_tiles, dL_drgb, dL_dalpha, dL_ddepth, T_final,
+                           last, blocks, g2d);
+    };
+    switch (cfg.window) {
+    case TS_WINDOW_SIGMOID: go(k_raster_bwd<TS_WINDOW_SIGMOID>); break;
+    case TS_WINDOW_LSE: go(k_raster_bwd<TS_WINDOW_LSE>); break;
+    default: go(k_raster_bwd<TS_WINDOW_PAPER>); break;
+    }
 }
 
 }  // namespace ts

@@ -1,0 +1,298 @@
+// train.hip -- the pieces of a training step around the renderer (Sec. 3.3):
+// the photometric loss (1 - lambda) L1 + lambda (1 - SSIM) and its image
+// gradient, the opacity and size losses, and Adam on the raw parameters.
+//
+// SSIM uses local statistics under an 11x11 Gaussian window; each of the two
+// SSIM kernels stages a 26x26 patch (a 16x16 tile and its 5-pixel halo,
+// zeros outside the image) in LDS and applies the separable window as a
+// row pass and a column pass.  Both are stencils bound by LDS traffic and
+// HBM; the optimizer kernels stream every parameter array once (HBM).
+#include <math.h>
+
+#include "ts_device.h"
+#include "ts_kernels.h"
+
+namespace ts {
+
+constexpr int kS = 16;            // output tile
+constexpr int kR = 5;             // window radius
+constexpr int kP = kS + 2 * kR;   // staged patch width
+constexpr float kC1 = 0.01f * 0.01f;
+constexpr float kC2 = 0.03f * 0.03f;
+
+struct Win11 {
+    float w[11];
+};
+
+// Row pass then column pass of the separable window over NQ staged
+// quantities: in[q][26][26] -> out[q] at this thread's pixel (ty, tx).
+template <int NQ>
+__device__ __forceinline__ void blur_patch(float (*in)[kP][kP], float (*row)[kP][kS],
+                                           const Win11& W, int tx, int ty, float* out)
+{
+    const int t = threadIdx.x;
+    // row pass: kP rows x kS columns per quantity
+    for (int e = t; e < NQ * kP * kS; e += 256) {
+        const int q = e / (kP * kS), r = (e / kS) % kP, c = e % kS;
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) acc = fmaf(W.w[k], in[q][r][c + k], acc);
+        row[q][r][c] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) acc = fmaf(W.w[k], row[q][ty + k][tx], acc);
+        out[q] = acc;
+    }
+}
+
+// Per pixel and channel: SSIM and the coefficients of its gradient,
+//   d_mx = dS/dmu_x - 2 mu_x dS/dvar_x - mu_y dS/dcov,  d_exx = dS/dvar_x,
+//   d_exy = dS/dcov,
+// scaled by the upstream -lambda / n; and the per-workgroup sums of |x - y|
+// and S (the loss value).
+__global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x_img,
+                                                  const float* __restrict__ y_img, int W, int H,
+                                                  Win11 win, float up, float* __restrict__ coef,
+                                                  float* __restrict__ part)
+{
+    __shared__ float in[5][kP][kP];
+    __shared__ float row[5][kP][kS];
+    __shared__ float red[2][8];
+    const int ch = blockIdx.z;
+    const int64_t hw = (int64_t)W * H;
+    const float* xc = x_img + ch * hw;
+    const float* yc = y_img + ch * hw;
+    const int x0 = blockIdx.x * kS - kR, y0 = blockIdx.y * kS - kR;
+    for (int e = threadIdx.x; e < kP * kP; e += 256) {
+        const int r = e / kP, c = e % kP, gx = x0 + c, gy = y0 + r;
+        const bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const float a = ok ? xc[(int64_t)gy * W + gx] : 0.f;
+        const float b = ok ? yc[(int64_t)gy * W + gx] : 0.f;
+        in[0][r][c] = a;
+        in[1][r][c] = b;
+        in[2][r][c] = a * a;
+        in[3][r][c] = b * b;
+        in[4][r][c] = a * b;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % kS, ty = threadIdx.x / kS;
+    float m[5];
+    blur_patch<5>(in, row, win, tx, ty, m);
+    const int px = blockIdx.x * kS + tx, py = blockIdx.y * kS + ty;
+    const bool inside = px < W && py < H;
+    float l1 = 0.f, s = 0.f;
+    if (inside) {
+        const float mx = m[0], my = m[1];
+        const float vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
+        const float A = 2.f * mx * my + kC1, Bn = 2.f * cxy + kC2;
+        const float D1 = mx * mx + my * my + kC1, D2 = vx + vy + kC2;
+        const float inv = 1.f / (D1 * D2);
+        s = A * Bn * inv;
+        const float dmx = 2.f * my * Bn * inv - s * 2.f * mx / D1;
+        const float dvx = -s / D2;
+        const float dcv = 2.f * A * inv;
+        const int64_t p = (int64_t)py * W + px;
+        float* cc = coef + ch * 3 * hw;
+        cc[p] = up * (dmx - 2.f * mx * dvx - my * dcv);
+        cc[hw + p] = up * dvx;
+        cc[2 * hw + p] = up * dcv;
+        l1 = fabsf(in[0][ty + kR][tx + kR] - in[1][ty + kR][tx + kR]);
+    }
+    // workgroup sums (wave reduction, then one value per wave)
+    for (int o = 32; o > 0; o >>= 1) {
+        l1 += __shfl_xor(l1, o);
+        s += __shfl_xor(s, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = l1;
+        red[1][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        part[2 * b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        part[2 * b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+// dL/dC = (1 - lambda) sign(x - y) / n + blur(d_mx) + 2 x blur(d_exx) + y blur(d_exy).
+__global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x_img,
+                                                  const float* __restrict__ y_img, int W, int H,
+                                                  Win11 win, float l1w,
+                                                  const float* __restrict__ coef,
+                                                  float* __restrict__ grad)
+{
+    __shared__ float in[3][kP][kP];
+    __shared__ float row[3][kP][kS];
+    const int ch = blockIdx.z;
+    const int64_t hw = (int64_t)W * H;
+    const float* cc = coef + ch * 3 * hw;
+    const int x0 = blockIdx.x * kS - kR, y0 = blockIdx.y * kS - kR;
+    for (int e = threadIdx.x; e < kP * kP; e += 256) {
+        const int r = e / kP, c = e % kP, gx = x0 + c, gy = y0 + r;
+        const bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int64_t p = (int64_t)gy * W + gx;
+        in[0][r][c] = ok ? cc[p] : 0.f;
+        in[1][r][c] = ok ? cc[hw + p] : 0.f;
+        in[2][r][c] = ok ? cc[2 * hw + p] : 0.f;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % kS, ty = threadIdx.x / kS;
+    float b[3];
+    blur_patch<3>(in, row, win, tx, ty, b);
+    const int px = blockIdx.x * kS + tx, py = blockIdx.y * kS + ty;
+    if (px >= W || py >= H) return;
+    const int64_t p = ch * hw + (int64_t)py * W + px;
+    const float x = x_img[p], y = y_img[p];
+    const float sg = x > y ? 1.f : (x < y ? -1.f : 0.f);
+    grad[p] = fmaf(l1w, sg, b[0] + 2.f * x * b[1] + y * b[2]);
+}
+
+// loss[0] = mean |x - y|, loss[1] = mean SSIM, from the per-workgroup sums
+// (one workgroup, fixed order: reproducible).
+__global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ part, int64_t nb,
+                                                    double n, float* __restrict__ loss)
+{
+    __shared__ double s[2][256];
+    double a = 0.0, b = 0.0;
+    for (int64_t j = threadIdx.x; j < nb; j += 256) {
+        a += part[2 * j];
+        b += part[2 * j + 1];
+    }
+    s[0][threadIdx.x] = a;
+    s[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + h];
+            s[1][threadIdx.x] += s[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss[0] = (float)(s[0][0] / n);
+        loss[1] = (float)(s[1][0] / n);
+    }
+}
+
+size_t image_loss_workspace_bytes(int W, int H)
+{
+    const int64_t tiles = (int64_t)((W + kS - 1) / kS) * ((H + kS - 1) / kS) * 3;
+    return (size_t)(9 * (int64_t)W * H * 4 + tiles * 8 + 256);
+}
+
+void launch_image_loss(const float* rgb, const float* target, int W, int H, float lambda,
+                       float* grad, float* loss, void* ws, hipStream_t stream)
+{
+    Win11 win;
+    double g[11], sum = 0.0;
+    for (int k = 0; k < 11; ++k) {
+        const double d = k - 5;
+        g[k] = exp(-d * d / (2.0 * 1.5 * 1.5));
+        sum += g[k];
+    }
+    for (int k = 0; k < 11; ++k) win.w[k] = (float)(g[k] / sum);
+    const double n = 3.0 * W * H;
+    const dim3 grid((W + kS - 1) / kS, (H + kS - 1) / kS, 3);
+    float* coef = reinterpret_cast<float*>(ws);
+    float* part = coef + 9 * (int64_t)W * H;
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, stream, rgb, target, W, H, win,
+                       (float)(-lambda / n), coef, part);
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, stream, rgb, target, W, H, win,
+                       (float)((1.0 - lambda) / n), coef, grad);
+    if (loss)
+        hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, stream, part,
+                           (int64_t)grid.x * grid.y * grid.z, n, loss);
+}
+
+// ---------------------------------------------------------------------------
+// Regularizers and the chain through the activations, per triangle:
+//   gv += beta_s d/dv mean 2/|c|, c = (v1 - v0) x (v2 - v0)
+//   ga = (go + beta_o / N) o (1 - o)      (o = sigmoid(a))
+//   gb = gsigma sigma                     (sigma = exp(b))
+// go and gsigma are overwritten with ga and gb.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_train_reg(const float* __restrict__ v,
+                                                   const float* __restrict__ o,
+                                                   const float* __restrict__ sigma, int64_t N,
+                                                   float beta_o, float beta_s,
+                                                   float* __restrict__ gv, float* __restrict__ go,
+                                                   float* __restrict__ gs)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    float p[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) p[a] = v[9 * i + a];
+    const float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+    const float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
+    const float c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                        e1[0] * e2[1] - e1[1] * e2[0]};
+    const float n2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    const float inv = rsqrtf(n2);
+    const float k = -2.f * beta_s / (float)N * inv * inv * inv;   // dL/dc = k c
+    const float gc[3] = {k * c[0], k * c[1], k * c[2]};
+    // c = e1 x e2: dL/de1 = e2 x gc, dL/de2 = gc x e1
+    const float g1[3] = {e2[1] * gc[2] - e2[2] * gc[1], e2[2] * gc[0] - e2[0] * gc[2],
+                         e2[0] * gc[1] - e2[1] * gc[0]};
+    const float g2[3] = {gc[1] * e1[2] - gc[2] * e1[1], gc[2] * e1[0] - gc[0] * e1[2],
+                         gc[0] * e1[1] - gc[1] * e1[0]};
+    const bool ok = n2 > 0.f && beta_s != 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float d1 = ok ? g1[a] : 0.f, d2 = ok ? g2[a] : 0.f;
+        gv[9 * i + a] -= d1 + d2;
+        gv[9 * i + 3 + a] += d1;
+        gv[9 * i + 6 + a] += d2;
+    }
+    const float oi = o[i];
+    go[i] = (go[i] + beta_o / (float)N) * oi * (1.f - oi);
+    gs[i] = gs[i] * sigma[i];
+}
+
+// Bias-corrected Adam over a flat array; element e uses lr_a when
+// e % row < first, else lr_b.  act 1 / 2 writes sigmoid / exp of the new
+// value to out (the renderer's activated copy).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ s,
+                                              int64_t n, int row, int first, float lr_a, float lr_b,
+                                              float b1, float b2, float bc1, float bc2, float eps,
+                                              int act, float* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float gi = g[e];
+    const float mi = fmaf(b1, m[e], (1.f - b1) * gi);
+    const float si = fmaf(b2, s[e], (1.f - b2) * gi * gi);
+    m[e] = mi;
+    s[e] = si;
+    const float lr = (int)(e % row) < first ? lr_a : lr_b;
+    const float pi = p[e] - lr * (mi / bc1) / (sqrtf(si / bc2) + eps);
+    p[e] = pi;
+    if (act == 1) out[e] = 1.f / (1.f + expf(-pi));
+    else if (act == 2) out[e] = expf(pi);
+}
+
+void launch_train_reg(const float* v, const float* o, const float* sigma, int64_t N, float beta_o,
+                      float beta_s, float* gv, float* go, float* gs, hipStream_t stream)
+{
+    if (N > 0)
+        hipLaunchKernelGGL(k_train_reg, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, v,
+                           o, sigma, N, beta_o, beta_s, gv, go, gs);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* s, int64_t n, int row, int first,
+                 float lr_a, float lr_b, float b1, float b2, float bc1, float bc2, float eps,
+                 int act, float* out, hipStream_t stream)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, g,
+                           m, s, n, row, first, lr_a, lr_b, b1, b2, bc1, bc2, eps, act, out);
+}
+
+}  // namespace ts

@@ -25,9 +25,13 @@ constexpr int kWave = 64;
 // u_k(p) = A_k dx + B_k dy + C_k with dx = px - ax, dy = py - ay exact
 // integers (the pixel centre's 1/2 is folded into C_k).
 //
+// The two alternative windows store the distance form instead: u_k(p) is
+// the signed distance from p to edge k (positive inside), the above times
+// the inradius r.
+//
 // Byte layout (16-byte chunks): 0-3 A, B, C[0..1]; 4 C[2], anchor, o;
-// 5 sigma, rgb; 6 z, tight box, index; 7 ut.  The rasterizers stage chunks
-// 0-5 and z in LDS.
+// 5 sigma, rgb; 6 z, tight box, index; 7 ut, phis.  The rasterizers stage
+// chunks 0-5 and z in LDS (and phis for the LogSumExp window).
 struct alignas(16) TriRecord {
     double A[3];
     double B[3];
@@ -40,12 +44,16 @@ struct alignas(16) TriRecord {
     int16_t px0, px1, py0, py1;  // tight pixel box
     uint32_t tri;
     float ut;     // lower bound of u over the pixels that can composite: u_min (1 - 2^-10)
-    float pad[3];
+    float phis;   // LogSumExp window: phi_lse(s) = ln 3 - r (< 0); else 0
+    float pad[2];
 };
 static_assert(sizeof(TriRecord) == 128, "record must be one 128-byte line");
 static_assert(offsetof(TriRecord, o) == 76 && offsetof(TriRecord, sigma) == 80 &&
-                  offsetof(TriRecord, z) == 96 && offsetof(TriRecord, ut) == 112,
+                  offsetof(TriRecord, z) == 96 && offsetof(TriRecord, ut) == 112 &&
+                  offsetof(TriRecord, phis) == 116,
               "chunk layout the rasterizers stage");
+
+constexpr double kLn3 = 1.0986122886681098;   // ln 3
 
 struct Cam {
     float R[9], t[3], fx, fy, cx, cy;
@@ -56,6 +64,7 @@ struct Cfg {
     float alpha_min, alpha_max, T_min, z_near, r_min;
     int deg;
     float bg[3];
+    int window;   // TS_WINDOW_*
 };
 
 // ---------------------------------------------------------------------------
@@ -134,11 +143,13 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z
 // the backward replay those of the forward bit for bit.
 // ---------------------------------------------------------------------------
 struct Frag {
-    float u;       // phi(p)/phi(s) (valid when > 0)
+    float u;       // phi(p)/phi(s) (valid when > 0); the sigmoid: distance inside
     float lg;      // log2(u)
     float I;       // window
+    float Ic;      // the sigmoid: 1 - I
     float oI;      // o * I before the clamp
     float a;       // alpha = min(alpha_max, o I)
+    float w[3];    // LogSumExp: softmax weights of the three edges
     int k;         // edge that attains the minimum
 };
 
@@ -163,6 +174,42 @@ __device__ __forceinline__ void window_alpha(double u64, float o, float sigma, f
     f.I = __builtin_amdgcn_exp2f(sigma * f.lg);   // v_exp_f32: 2^x
     f.oI = o * f.I;
     f.a = fminf(alpha_max, f.oI);
+}
+
+// Sigmoid window (Eq. 2) at signed distance d inside the triangle (pixels):
+// I = 1 / (1 + e), e = exp(-d / sigma), and 1 - I = e I.
+__device__ __forceinline__ void sigmoid_alpha(double d64, float o, float sigma, float alpha_max,
+                                              Frag& f)
+{
+    f.u = (float)d64;
+    // 2^(-d log2(e) / sigma), the exponent capped at 64 so e stays finite
+    // (I < 6e-20 beyond) and 1 - I = e I never becomes inf * 0
+    const float e = __builtin_amdgcn_exp2f(
+        fminf(f.u * __builtin_amdgcn_rcpf(sigma) * -1.4426950408889634f, 64.f));
+    f.I = __builtin_amdgcn_rcpf(1.f + e);
+    f.Ic = e * f.I;
+    f.oI = o * f.I;
+    f.a = fminf(alpha_max, f.oI);
+}
+
+// LogSumExp SDF in the window of Eq. 1: with d_k the distances inside,
+// phi_lse = log sum_k exp(-d_k) = log sum_k exp(m - d_k) - m, m = min_k d_k
+// (every exponent <= 0), u = phi_lse / phi_lse(s).  FP64 up to u: near the
+// support's edge phi_lse is a small difference.  Returns u.
+__device__ __forceinline__ double lse_u(const double* A, const double* B, const double* C,
+                                        double dx, double dy, double phis, Frag& f)
+{
+    int k;
+    const double m = edge_min(A, B, C, dx, dy, k);
+    double e[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) e[j] = exp(m - fma(A[j], dx, fma(B[j], dy, C[j])));
+    const double sum = (e[0] + e[1]) + e[2];
+    const double inv = 1.0 / sum;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) f.w[j] = (float)(e[j] * inv);
+    f.k = k;
+    return (log(sum) - m) / phis;
 }
 
 }  // namespace ts

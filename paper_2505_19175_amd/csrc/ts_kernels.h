@@ -4,12 +4,35 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ts.h"
 
 namespace ts {
 
 struct Cam;
 struct Cfg;
+
+// Calls L<DEG, WIN>::run(args...) for a runtime SH degree (0..3) and window
+// function (TS_WINDOW_*): one kernel instantiation per pair.
+template <template <int, int> class L, typename... Args>
+void dispatch_deg_win(int deg, int win, Args&&... args)
+{
+    auto by_win = [&](auto deg_c) {
+        constexpr int D = decltype(deg_c)::value;
+        switch (win) {
+        case TS_WINDOW_SIGMOID: L<D, TS_WINDOW_SIGMOID>::run(args...); break;
+        case TS_WINDOW_LSE: L<D, TS_WINDOW_LSE>::run(args...); break;
+        default: L<D, TS_WINDOW_PAPER>::run(args...); break;
+        }
+    };
+    switch (deg) {
+    case 0: by_win(std::integral_constant<int, 0>{}); break;
+    case 1: by_win(std::integral_constant<int, 1>{}); break;
+    case 2: by_win(std::integral_constant<int, 2>{}); break;
+    default: by_win(std::integral_constant<int, 3>{}); break;
+    }
+}
 
 void launch_project(const float* v, const float* o, const float* sigma, const float* sh,
                     int64_t N, const Cam& cam, const Cfg& cfg, void* rec, int16_t* rect,
@@ -70,6 +93,24 @@ void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t
                            int num_tiles, float* rgb, float* alpha, float* depth, float* T_final,
                            uint32_t* last, uint16_t* blocks, float* max_weight, uint32_t* pixels,
                            hipStream_t stream);
+
+// Densification (Sec. 3.2): sampling and midpoint subdivision.
+size_t densify_workspace_bytes(int64_t N);
+void launch_densify_select(const float* o, const float* sigma, int64_t N, int mode, double k,
+                           const float* u, uint8_t* sel, void* ws, hipStream_t stream);
+void launch_densify_subdivide(float* v, float* o, float* sigma, float* sh, int nsh, int64_t N,
+                              int64_t capacity, const uint8_t* sel, void* ws, uint32_t* d_out,
+                              hipStream_t stream);
+
+// Training step pieces (Sec. 3.3): image loss, regularizers, Adam.
+size_t image_loss_workspace_bytes(int W, int H);
+void launch_image_loss(const float* rgb, const float* target, int W, int H, float lambda,
+                       float* grad, float* loss, void* ws, hipStream_t stream);
+void launch_train_reg(const float* v, const float* o, const float* sigma, int64_t N, float beta_o,
+                      float beta_s, float* gv, float* go, float* gs, hipStream_t stream);
+void launch_adam(float* p, const float* g, float* m, float* s, int64_t n, int row, int first,
+                 float lr_a, float lr_b, float b1, float b2, float bc1, float bc2, float eps,
+                 int act, float* out, hipStream_t stream);
 
 // views[i] += pixels[i] > 1; pixels[i] = 0.
 void launch_prune_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream);

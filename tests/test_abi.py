@@ -52,9 +52,10 @@ PROBE = r"""
 #define P(T, F) printf(#T "." #F " %zu\n", offsetof(T, F))
 int main(void) {
   printf("ts_camera %zu\n", sizeof(ts_camera)); P(ts_camera, t); P(ts_camera, fx); P(ts_camera, width);
-  printf("ts_config %zu\n", sizeof(ts_config)); P(ts_config, sh_degree); P(ts_config, bg);
+  printf("ts_config %zu\n", sizeof(ts_config)); P(ts_config, sh_degree); P(ts_config, bg); P(ts_config, window);
   printf("ts_proj %zu\n", sizeof(ts_proj)); P(ts_proj, g2d); P(ts_proj, cgrad);
   printf("ts_bins %zu\n", sizeof(ts_bins)); P(ts_bins, d_count); P(ts_bins, capacity); P(ts_bins, order); P(ts_bins, blocks);
+  printf("ts_prune_stats %zu\n", sizeof(ts_prune_stats)); P(ts_prune_stats, pixels);
   printf("ts_view %zu\n", sizeof(ts_view)); P(ts_view, tile_offset); P(ts_view, tiles_x); P(ts_view, pixel_offset);
   return 0;
 }
@@ -71,7 +72,7 @@ def test_struct_layouts_match_header():
         lines = subprocess.check_output([exe], text=True).split("\n")
     got = dict(l.split() for l in lines if l)
     ct = {"ts_camera": B.ts_camera, "ts_config": B.ts_config, "ts_proj": B.ts_proj,
-          "ts_bins": B.ts_bins, "ts_view": B.ts_view}
+          "ts_bins": B.ts_bins, "ts_view": B.ts_view, "ts_prune_stats": B.ts_prune_stats}
     for k, v in got.items():
         if "." in k:
             s, f = k.split(".")

@@ -1,0 +1,138 @@
+"""GPU parity of the densification step (Sec. 3.2, "Densification") against
+the oracle: Bernoulli selection bit-exact (decisions within 1e-12 of their
+threshold are flagged and counted instead), midpoint subdivision bit-exact,
+on a small soup, a soup that triggers the cap at one, and the 3M-triangle
+soup; overflow leaves the soup untouched."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import densify as D
+from paper_2505_19175_amd import binding as B
+from paper_2505_19175_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV)
+
+
+def _select(o, s, mode, k, u):
+    N = o.size
+    ws_bytes = B.ts_densify_workspace_bytes(N)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=DEV)
+    sel = torch.zeros(max(N, 1), dtype=torch.uint8, device=DEV)
+    B.ts_densify_select(_t(o), _t(s), N, mode, k, _t(u), sel, ws, ws_bytes)
+    torch.cuda.synchronize()
+    return sel.cpu().numpy()[:N].astype(bool)
+
+
+def _check_select(o, s, mode, k, u):
+    got = _select(o, s, mode, k, u)
+    p = D.probabilities(o, s, mode, k)
+    want = D.select(o, s, mode, k, u)
+    near = np.abs(u.astype(np.float64) - p) <= 1e-12 * np.maximum(p, 1e-300)
+    assert near.sum() <= 2
+    np.testing.assert_array_equal(got[~near], want[~near])
+    return int(want.sum())
+
+
+@pytest.mark.parametrize("mode", [B.TS_DENSIFY_OPACITY, B.TS_DENSIFY_INV_SIGMA])
+def test_select_small(mode):
+    rng = np.random.default_rng(5 + mode)
+    N = 10000
+    o = rng.uniform(0.0, 1.0, N).astype(np.float32)
+    s = rng.uniform(0.2, 5.0, N).astype(np.float32)
+    u = rng.random(N).astype(np.float32)
+    n = _check_select(o, s, mode, 1000.0, u)
+    assert 850 < n < 1150
+
+
+def test_select_cap_and_degenerate():
+    rng = np.random.default_rng(9)
+    N = 3000
+    o = rng.uniform(0.0, 0.01, N).astype(np.float32)
+    o[:5] = 1.0                                     # p = 1 for these at k = 200
+    s = np.ones(N, np.float32)
+    u = rng.random(N).astype(np.float32)
+    assert _check_select(o, s, B.TS_DENSIFY_OPACITY, 200.0, u) >= 5
+    assert not _select(np.zeros(N, np.float32), s, B.TS_DENSIFY_OPACITY, 50.0, u).any()
+    assert not _select(o, s, B.TS_DENSIFY_OPACITY, 0.0, u).any()
+    # ragged sizes around the workgroup and the partial-sum chunk
+    for N in (1, 255, 257, 4095, 4097):
+        _check_select(o[:N] + 0.5, s[:N], B.TS_DENSIFY_INV_SIGMA, N / 7.0, u[:N])
+
+
+def _subdivide(v, o, s, sh, deg, sel, capacity, host=True):
+    N = o.size
+    K = (deg + 1) ** 2
+    tv = torch.zeros((capacity, 3, 3), dtype=torch.float32, device=DEV)
+    to = torch.zeros(capacity, dtype=torch.float32, device=DEV)
+    ts_ = torch.zeros(capacity, dtype=torch.float32, device=DEV)
+    tsh = torch.zeros((capacity, K, 3), dtype=torch.float32, device=DEV)
+    tv[:N], to[:N], ts_[:N], tsh[:N] = _t(v), _t(o), _t(s), _t(sh)
+    ws_bytes = B.ts_densify_workspace_bytes(N)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=DEV)
+    d = torch.zeros(2, dtype=torch.int32, device=DEV)
+    hc = (ctypes.c_uint32 * 2)() if host else None
+    B.ts_densify_subdivide(tv, to, ts_, tsh, deg, N, capacity, _t(sel.astype(np.uint8)), ws,
+                           ws_bytes, d, hc)
+    torch.cuda.synchronize()
+    return (tv.cpu().numpy(), to.cpu().numpy(), ts_.cpu().numpy(), tsh.cpu().numpy(),
+            d.cpu().numpy().view(np.uint32))
+
+
+def _soup(seed, N, deg):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(0, 2, (N, 3, 3)).astype(np.float32)
+    o = rng.uniform(0.01, 1, N).astype(np.float32)
+    s = rng.uniform(0.3, 3, N).astype(np.float32)
+    sh = rng.normal(0, 1, (N, (deg + 1) ** 2, 3)).astype(np.float32)
+    return v, o, s, sh
+
+
+@pytest.mark.parametrize("N,deg", [(1, 0), (300, 1), (5000, 3)])
+def test_subdivide_bit_exact(N, deg):
+    v, o, s, sh = _soup(11, N, deg)
+    sel = np.random.default_rng(12).random(N) < 0.3
+    sel[0] = True
+    n = int(sel.sum())
+    gv, go, gs, gsh, d = _subdivide(v, o, s, sh, deg, sel, N + 3 * n + 7)
+    wv, wo, ws_, wsh = D.subdivide(v, o, s, sh, sel)
+    M = N + 3 * n
+    assert d[0] == M and d[1] == 0
+    assert np.array_equal(gv[:M], wv) and np.array_equal(go[:M], wo)
+    assert np.array_equal(gs[:M], ws_) and np.array_equal(gsh[:M], wsh)
+    assert not gv[M:].any()                    # nothing past the new count
+
+
+def test_subdivide_overflow_leaves_soup():
+    v, o, s, sh = _soup(13, 400, 1)
+    sel = np.random.default_rng(14).random(400) < 0.5
+    cap = 400 + 3 * int(sel.sum()) - 1
+    gv, go, gs, gsh, d = _subdivide(v, o, s, sh, 1, sel, cap, host=False)
+    assert d[1] == 1 and np.array_equal(gv[:400], v) and not gv[400:].any()
+    with pytest.raises(B.TSError) as e:
+        _subdivide(v, o, s, sh, 1, sel, cap, host=True)
+    assert e.value.code == B.TS_ECAPACITY
+
+
+def test_densify_3m_soup():
+    """The 3M-triangle, SH-3 soup: select 10% by inverse sigma (30% more
+    triangles after the split), then subdivide; everything bit-exact."""
+    sc = synth.workload_large().scene
+    N = sc.n
+    u = np.random.default_rng(21).random(N).astype(np.float32)
+    n = _check_select(sc.o, sc.sigma, B.TS_DENSIFY_INV_SIGMA, 0.1 * N, u)
+    sel = _select(sc.o, sc.sigma, B.TS_DENSIFY_INV_SIGMA, 0.1 * N, u)
+    gv, go, gs, gsh, d = _subdivide(sc.v, sc.o, sc.sigma, sc.sh, 3, sel, N + 3 * n + 16)
+    wv, wo, ws_, wsh = D.subdivide(sc.v, sc.o, sc.sigma, sc.sh, sel)
+    M = N + 3 * int(sel.sum())
+    assert d[0] == M
+    assert np.array_equal(gv[:M], wv) and np.array_equal(go[:M], wo)
+    assert np.array_equal(gs[:M], ws_) and np.array_equal(gsh[:M], wsh)

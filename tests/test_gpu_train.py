@@ -1,0 +1,153 @@
+"""GPU parity of the training-step pieces (Sec. 3.3) against the oracle:
+the image loss and its gradient, the regularizers with the activation chain
+and Adam over two steps, and a short fit of a synthetic target whose loss
+must fall."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import train as TR
+from paper_2505_19175_amd import binding as B
+from paper_2505_19175_amd import synth
+from paper_2505_19175_amd.render import Rasterizer, ViewState, scene_to_device
+from paper_2505_19175_amd.train import DEFAULTS, TrainState
+
+import gpu_util as G
+from helpers import random_soup as _soup64
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(DEV)
+
+
+def _gpu_image_loss(C, T, lam):
+    H, W = C.shape[1], C.shape[2]
+    need = B.ts_image_loss_workspace_bytes(W, H)
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    g = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
+    loss = torch.zeros(2, dtype=torch.float32, device=DEV)
+    B.ts_image_loss(_t(C), _t(T), W, H, lam, g, loss, ws, need)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), loss.cpu().numpy().astype(np.float64)
+
+
+def _close(got, want, rel=1e-3, floor=1e-5, l2=1e-3):
+    scale = np.abs(want).max()
+    bad = np.abs(got - want) > rel * np.abs(want) + floor * scale
+    err = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    assert bad.sum() == 0 and err <= l2, (int(bad.sum()), err)
+    return err
+
+
+@pytest.mark.parametrize("W,H", [(16, 16), (45, 37), (128, 96)])
+@pytest.mark.parametrize("lam", [0.0, 0.2, 1.0])
+def test_image_loss(W, H, lam):
+    """Random images with ragged sizes: one tile, several tiles with a
+    ragged edge, and more tiles than the window's reach."""
+    rng = np.random.default_rng(W + H)
+    T = rng.random((3, H, W))
+    C = np.clip(T + rng.normal(0, 0.15, T.shape), 0, 1)
+    C32, T32 = C.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64)
+    g, loss = _gpu_image_loss(C32, T32, lam)
+    want = TR.image_loss_grad(C32, T32, lam)
+    err = _close(g, want)
+    assert loss[0] == pytest.approx(np.mean(np.abs(C32 - T32)), rel=1e-6)
+    assert loss[1] == pytest.approx(np.mean(TR.ssim_map(C32, T32)), abs=2e-6)
+    print("image loss", W, H, lam, err)
+
+
+def test_image_loss_of_a_render():
+    """A rendered image against the render of a moved copy of the soup
+    (large flat regions of background: the sign(0) case of L1)."""
+    sc, cam = _soup64(51, 120, W=80, H=64, deg=1, dtype=np.float32)
+    cfg = synth.Config(sh_degree=1)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    sc2 = dataclasses.replace(sc, v=(sc.v + np.float32(0.02)).astype(np.float32))
+    ras2, st2, sct2, out2 = G.gpu_forward(sc2, cam, cfg)
+    C = out.rgb.cpu().numpy().astype(np.float64)
+    T = out2.rgb.cpu().numpy().astype(np.float64)
+    g, loss = _gpu_image_loss(C, T, 0.2)
+    _close(g, TR.image_loss_grad(C, T, 0.2))
+
+
+def _random_params(seed, N, deg):
+    rng = np.random.default_rng(seed)
+    K = (deg + 1) ** 2
+    raw = {"v": rng.normal(0, 1, (N, 3, 3)).astype(np.float32),
+           "a": rng.normal(0, 1.5, N).astype(np.float32),
+           "b": rng.normal(0, 0.5, N).astype(np.float32),
+           "sh": rng.normal(0, 1, (N, K, 3)).astype(np.float32)}
+    grads = {"v": rng.normal(0, 1e-2, (N, 3, 3)).astype(np.float32),
+             "o": rng.normal(0, 1e-1, N).astype(np.float32),
+             "sigma": rng.normal(0, 1e-1, N).astype(np.float32),
+             "sh": rng.normal(0, 1e-2, (N, K, 3)).astype(np.float32)}
+    return raw, grads
+
+
+@pytest.mark.parametrize("N,deg", [(1, 0), (1000, 1), (70001, 3)])
+def test_optimizer_two_steps(N, deg):
+    raw, grads = _random_params(N, N, deg)
+    beta_s = 1e-3                    # large enough for the size term to show
+    o = TR.sigmoid(raw["a"]).astype(np.float32)
+    s = np.exp(raw["b"].astype(np.float64)).astype(np.float32)
+    dv, da, db, dsh = (_t(raw[k]) for k in ("v", "a", "b", "sh"))
+    do_, ds = _t(o), _t(s)
+    mom = [torch.zeros_like(x) for x in (dv, dv, da, da, db, db, dsh, dsh)]
+    st = B.ts_adam_state(*(m.data_ptr() for m in mom))
+    cfg = {k: v for k, v in DEFAULTS.items() if k != "lam"}
+    cfg["beta_size"] = beta_s
+    ref_raw = {k: raw[k].astype(np.float64) for k in raw}
+    ref_state = {k: (np.zeros(np.shape(raw[k])), np.zeros(np.shape(raw[k]))) for k in raw}
+    lr = dict(TR.LR)
+    for t in (1, 2):
+        gv, go, gs, gsh = (_t(grads[k]) for k in ("v", "o", "sigma", "sh"))
+        opt = B.ts_optimizer(**{k: float(v) for k, v in cfg.items()}, step=t)
+        B.ts_optimizer_step(dv, da, db, dsh, do_, ds, deg, N, gv, go, gs, gsh, st, opt)
+        torch.cuda.synchronize()
+        ref_raw, ref_state = TR.optimizer_step(
+            {"v": ref_raw["v"], "a": ref_raw["a"], "b": ref_raw["b"], "sh": ref_raw["sh"]},
+            {k: grads[k].astype(np.float64) for k in grads},
+            ref_state, t, lr, beta_o=DEFAULTS["beta_opacity"], beta_s=beta_s)
+        # the gradients were fed in float32 at the float32 parameters of the GPU
+        ref_raw = {k: ref_raw[k] for k in ref_raw}
+        for k, d in (("v", dv), ("a", da), ("b", db), ("sh", dsh)):
+            got = d.cpu().numpy().astype(np.float64)
+            step_size = max(lr.values()) * t
+            np.testing.assert_allclose(got, ref_raw[k], rtol=0, atol=1e-6 + 1e-4 * step_size,
+                                       err_msg=f"{k} t={t}")
+        np.testing.assert_allclose(do_.cpu().numpy(), TR.sigmoid(ref_raw["a"]), atol=2e-7)
+        np.testing.assert_allclose(ds.cpu().numpy(), np.exp(ref_raw["b"]), rtol=2e-6)
+        for (m_k, s_k), (m_r, s_r) in zip([(mom[0], mom[1]), (mom[2], mom[3]), (mom[4], mom[5]),
+                                           (mom[6], mom[7])],
+                                          [ref_state[k] for k in ("v", "a", "b", "sh")]):
+            # the size-loss gradient is FP32 on the GPU (cross products of
+            # nearby vertices): ~1e-5 relative in g, twice that in g^2
+            np.testing.assert_allclose(m_k.cpu().numpy(), m_r, rtol=5e-5, atol=1e-12)
+            np.testing.assert_allclose(s_k.cpu().numpy(), s_r, rtol=1e-4, atol=1e-14)
+
+
+def test_fit_lowers_the_loss():
+    """Fit a soup to the render of a displaced copy of itself: 40 steps of
+    the full device step; the loss must fall by 15%."""
+    sc, cam = _soup64(61, 300, W=96, H=80, size=0.8, deg=1, o=(0.3, 0.9), dtype=np.float32)
+    cfg = synth.Config(sh_degree=1)
+    ras = Rasterizer(cfg, device=DEV)
+    tgt_scene = dataclasses.replace(sc, v=(sc.v + np.random.default_rng(1).normal(
+        0, 0.03, sc.v.shape)).astype(np.float32))
+    st_t = ViewState(sc.n, cam.width, cam.height, 1 << 16, device=DEV)
+    target = ras.forward(st_t, scene_to_device(tgt_scene, DEV), cam).rgb.clone()
+    ts = TrainState(sc, device=DEV, lr_v=0.003)
+    st = ViewState(sc.n, cam.width, cam.height, 1 << 16, device=DEV)
+    losses = []
+    for k in range(40):
+        ts.step(ras, st, cam, target, sync=True)
+        torch.cuda.synchronize()
+        losses.append(ts.loss_value())
+    assert losses[-1] < 0.85 * losses[0], losses
+    assert np.isfinite(losses).all()

@@ -1,0 +1,101 @@
+"""GPU parity of the two window alternatives of Sec. 3.1 (the sigmoid of
+Eq. 2 and Eq. 1 with a LogSumExp SDF) against the oracle: projection and
+bins bit-exact, forward to 1e-5, gradients to the gradient bar, on a soup of
+large overlapping triangles (inradius well above ln 3 px), the 20k-triangle
+sigma sweep and sampled pixels of the 3M-triangle view."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2505_19175_amd import binding as B
+from paper_2505_19175_amd import synth
+from paper_2505_19175_amd.synth import WINDOW_LSE, WINDOW_SIGMOID, Config
+
+import gpu_util as G
+from helpers import random_soup as _soup64
+from test_gpu_parity import _check_bins, _check_projection, _sampled
+
+pytestmark = pytest.mark.gpu
+
+WINDOWS = [WINDOW_SIGMOID, WINDOW_LSE]
+NAMES = {WINDOW_SIGMOID: "sigmoid", WINDOW_LSE: "lse"}
+# Largest fraction of pixels the oracle may flag (a decision within rounding
+# of alpha_min, T_min or a depth tie).  The sigmoid's long tails put 80-200
+# fragments on a pixel, many of them near the cut-off: up to ~5.4% of the
+# pixels of the sigma = 4 sweep and ~4.7% of the 3M-triangle sample.
+MAX_FLAG = {WINDOW_SIGMOID: 0.08, WINDOW_LSE: 0.01}
+
+
+def _full(scene, cam, cfg, seed, alpha_depth=True):
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    nvis = _check_projection(st, scene, cam, cfg)
+    M = _check_bins(st, scene, cam, cfg)
+    ref_f = O.render(scene, cam, cfg)
+    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref_f, max_flag_frac=MAX_FLAG[cfg.window])
+    dC, dA, dD = synth.upstream(seed, cam.width, cam.height, alpha_depth, alpha_depth)
+    keep = ref_f["flag"] == 0
+    dC = dC * keep[None]
+    dA = None if dA is None else dA * keep
+    dD = None if dD is None else dD * keep
+    g = G.gpu_backward(ras, st, sct, out, dC, dA, dD)
+    r = O.backward(scene, cam, cfg, dC, dA, dD)
+    return nvis, M, n_ok, n_flag, worst, G.assert_grads(g, r)
+
+
+@pytest.mark.parametrize("window", WINDOWS, ids=[NAMES[w] for w in WINDOWS])
+def test_large_triangles(window):
+    """600 triangles of 20-40 px in a 160x120 image: deep overlap, supports
+    that reach past the triangle (sigmoid) or stay inside it (LogSumExp)."""
+    sc, cam = _soup64(41, 600, W=160, H=120, size=1.0, deg=1, sigma=(0.25, 4.0),
+                      o=(0.05, 1.0), dtype=np.float32)
+    cfg = Config(sh_degree=1, bg=(0.1, 0.2, 0.3), window=window)
+    nvis, M, n_ok, n_flag, worst, s = _full(sc, cam, cfg, 201)
+    assert nvis > 500 and M > 4 * nvis
+    print(NAMES[window], nvis, M, n_ok, n_flag, worst, s)
+
+
+@pytest.mark.parametrize("window", WINDOWS, ids=[NAMES[w] for w in WINDOWS])
+@pytest.mark.parametrize("sigma", [0.25, 1.0, 4.0])
+def test_grad_workload(window, sigma):
+    """The 20k-triangle, 256x256 sweep with each alternative window (the
+    LogSumExp window culls the triangles with inradius <= ln 3 px)."""
+    wl = synth.workload_grad(sigma)
+    cfg = dataclasses.replace(wl.config, window=window)
+    nvis, M, n_ok, n_flag, worst, s = _full(wl.scene, wl.cameras[0], cfg, wl.upstream_seed)
+    print(NAMES[window], sigma, nvis, M, n_ok, n_flag, worst, s)
+
+
+def test_small_triangles_cull_under_lse():
+    """Under LogSumExp a triangle with inradius <= ln 3 px has no inside:
+    the 1k-triangle scene (inradii around 1 px) keeps only the larger ones,
+    and both sides agree on which."""
+    wl = synth.workload_small()
+    cfg = dataclasses.replace(wl.config, window=WINDOW_LSE)
+    ras, st, sct, out = G.gpu_forward(wl.scene, wl.cameras[0], cfg)
+    nvis = _check_projection(st, wl.scene, wl.cameras[0], cfg)
+    ref = O.setup(wl.scene, wl.cameras[0], wl.config)
+    assert 0 < nvis < int((ref["ntiles"] > 0).sum())
+    assert np.all(ref["r"][st.ntiles.cpu().numpy()[: wl.scene.n] > 0] > np.log(3.0))
+
+
+@pytest.mark.parametrize("window", WINDOWS, ids=[NAMES[w] for w in WINDOWS])
+def test_large_workload_sampled(window):
+    """3M triangles at 1280x720 (the benchmarked view) on sampled pixels."""
+    wl = synth.workload_large()
+    cfg = dataclasses.replace(wl.config, window=window)
+    st, n_ok, n_flag, worst, s = _sampled(wl.scene, wl.cameras[0], cfg, 31 + window, n_pix=1024,
+                                          max_flag_frac=MAX_FLAG[window])
+    print(NAMES[window], st.M, st.N_v, n_ok, n_flag, worst, s)
+
+
+def test_window_out_of_range_is_rejected():
+    sc, cam = _soup64(44, 10, W=32, H=32, dtype=np.float32)
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    bad = B.make_config(cfg)
+    bad.window = 3
+    with pytest.raises(B.TSError) as e:
+        B.ts_project(*sct, sc.n, B.make_camera(cam), bad, st.proj)
+    assert e.value.code == B.TS_EINVAL

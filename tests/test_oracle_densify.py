@@ -141,10 +141,11 @@ MUTANTS = [
     ("select on >=", "return np.asarray(u, np.float64) < probabilities(",
      "return np.asarray(u, np.float64) >= probabilities("),
     ("wrong corner child", "np.stack([v0, m01, m20], -2),", "np.stack([v0, m01, m12], -2),"),
-    ("centre child skipped", "out_v[i] = ch[0]", "out_v[i] = v[i]"),
-    ("children without the parent's sigma", "out_o[j], out_s[j], out_sh[j] = o[i], sigma[i], sh[i]",
-     "out_o[j], out_sh[j] = o[i], sh[i]"),
-    ("append order", "j = N + 3 * r + c", "j = N + r + 3 * c"),
+    ("centre child skipped", "out_v[idx] = ch[:, 0]", "out_v[idx] = v[idx]"),
+    ("children without the parent's sigma",
+     "out_o[j], out_s[j], out_sh[j] = np.asarray(o)[idx], np.asarray(sigma)[idx], np.asarray(sh)[idx]",
+     "out_o[j], out_sh[j] = np.asarray(o)[idx], np.asarray(sh)[idx]"),
+    ("append order", "j = N + 3 * np.arange(n) + c", "j = N + np.arange(n) + n * c"),
 ]
 
 
