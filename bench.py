@@ -31,7 +31,8 @@ G_REC = 48      # 2D gradient record (bytes)
 
 # HBM traffic of one launch of a kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of `bench.py --steps 2 --warmup 1 --no-cpu-baseline
-# --no-serve` (KiB per dispatch), each scaled by what the same counter reads
+# --no-serve --no-other-view --no-windows --no-prune-stats` (KiB per dispatch
+# of the benchmarked step's launches), each scaled by what the same counter reads
 # for a 512 MiB device copy (`bench.py --copy-probe`: FETCH_SIZE reads half
 # the copied bytes, WRITE_SIZE all of them).  Valid only for the kernel
 # source the counters were taken on: `src` is the SHA-256 of its files.
@@ -39,14 +40,14 @@ TRAFFIC = {
     "project_bwd": {"files": ["paper_2505_19175_amd/csrc/backproject.hip",
                               "paper_2505_19175_amd/csrc/geometry.h",
                               "paper_2505_19175_amd/csrc/ts_device.h"],
-                    "src": "3426376331313e629ea5383194261babc61f7b809c59e0106dbf1e7e3664f3d4",
-                    "fetch_kib": 1.615e5, "write_kib": 7.807e5,
+                    "src": "4c680e1b02aeef36b033cfd8e0038c28be8cb3250c7e7d9a2c3d815462bb4bb7",
+                    "fetch_kib": 1.6148e5, "write_kib": 7.8067e5,
                     "fetch_scale": 2.0, "write_scale": 1.0},
     "project": {"files": ["paper_2505_19175_amd/csrc/project.hip",
                           "paper_2505_19175_amd/csrc/geometry.h",
                           "paper_2505_19175_amd/csrc/ts_device.h"],
-                "src": "8900049176f58d32fe6851a145d1e1cb683809b13b89a2fb857488ada26c8b42",
-                "fetch_kib": 2.148e5, "write_kib": 3.101e5,
+                "src": "ad298663041bdf233606a97e034e3f4754496437959e0e84a3ba9abc8e133f22",
+                "fetch_kib": 2.1484e5, "write_kib": 3.1017e5,
                 "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
