@@ -89,21 +89,21 @@ __global__ __launch_bounds__(kDensBlock) void k_scan_sel(uint32_t* __restrict__ 
     const int64_t lo = min(nb, t * per), hi = min(nb, lo + per);
     uint64_t acc = 0;
     for (int64_t j = lo; j < hi; ++j) acc += cnt[j];
+    // inclusive scan of the 256 chunk sums (log-step, two barriers a step)
     s[t] = acc;
     __syncthreads();
-    if (t == 0) {   // 256 partial sums: a short serial scan
-        uint64_t run = 0;
-        for (int j = 0; j < kDensBlock; ++j) {
-            const uint64_t x = s[j];
-            s[j] = run;
-            run += x;
-        }
-        const uint64_t total = (uint64_t)N + 3 * run;
+    for (int off = 1; off < kDensBlock; off <<= 1) {
+        const uint64_t x = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += x;
+        __syncthreads();
+    }
+    if (t == kDensBlock - 1) {
+        const uint64_t total = (uint64_t)N + 3 * s[t];
         out[0] = (uint32_t)min(total, (uint64_t)0xffffffffu);
         out[1] = total > (uint64_t)capacity ? 1u : 0u;
     }
-    __syncthreads();
-    uint64_t run = s[t];
+    uint64_t run = s[t] - acc;
     for (int64_t j = lo; j < hi; ++j) {
         const uint32_t x = cnt[j];
         cnt[j] = (uint32_t)run;
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kDensBlock) void k_subdivide(
     __shared__ uint32_t s_w[kDensBlock / kWave];
     if (out[1] != 0u) return;   // does not fit: leave the soup unchanged
     const int64_t i = (int64_t)blockIdx.x * kDensBlock + threadIdx.x;
+    const bool vec = (nsh & 3) == 0 && (reinterpret_cast<uintptr_t>(sh) & 15u) == 0;
     const bool me = i < N && sel[i] != 0;
     const uint64_t m = __ballot(me);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -132,8 +133,23 @@ __global__ __launch_bounds__(kDensBlock) void k_subdivide(
     __syncthreads();
     uint32_t before = 0;
     for (int j = 0; j < w; ++j) before += s_w[j];
-    if (!me) return;
     const int64_t r = (int64_t)off[blockIdx.x] + before + below;
+    if (vec) {
+        // SH rows of whole 16-byte vectors (degrees 1 and 3): the wave copies
+        // each selected lane's row to its three corner children together --
+        // they are consecutive, so one wave store covers 3 rows contiguously
+        const int n4 = nsh / 4;
+        uint64_t todo = m;
+        while (todo) {
+            const int L = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int64_t src_i = __shfl(i, L), dst_r = __shfl(r, L);
+            const float4* s4 = reinterpret_cast<const float4*>(sh + (int64_t)nsh * src_i);
+            float4* d4 = reinterpret_cast<float4*>(sh + (int64_t)nsh * (N + 3 * dst_r));
+            for (int q = lane; q < 3 * n4; q += kWave) d4[q] = s4[q % n4];
+        }
+    }
+    if (!me) return;
 
     float p[9];
 #pragma unroll
@@ -165,19 +181,8 @@ __global__ __launch_bounds__(kDensBlock) void k_subdivide(
         o[j0 + c] = oi;
         sigma[j0 + c] = si;
     }
+    if (vec) return;   // copied by the wave above
     const float* src = sh + (int64_t)nsh * i;
-    if ((nsh & 3) == 0 && (reinterpret_cast<uintptr_t>(sh) & 15u) == 0) {
-        // rows of whole 16-byte vectors (SH degrees 1 and 3): vector copies
-        const float4* s4 = reinterpret_cast<const float4*>(src);
-        float4* d4 = reinterpret_cast<float4*>(sh + (int64_t)nsh * j0);
-        const int n4 = nsh / 4;
-        for (int q = 0; q < n4; ++q) {
-            const float4 x = s4[q];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) d4[c * n4 + q] = x;
-        }
-        return;
-    }
     for (int q = 0; q < nsh; ++q) {
         const float x = src[q];
 #pragma unroll

@@ -41,8 +41,20 @@ struct StageExtra<TS_WINDOW_LSE> {
     float ps[kBatch];
 };
 
-template <int WIN>
-struct StageT : StageExtra<WIN> {
+// Per-entry pruning statistics of a batch (the forward that keeps them
+// only): largest T*o (float bits; non-negative floats order as integers)
+// and composited pixels over the tile, flushed with one global atomic pair
+// per entry at the end of the batch.
+template <bool ST>
+struct StatsExtra {};
+template <>
+struct StatsExtra<true> {
+    uint32_t mw[kBatch];
+    uint32_t px[kBatch];
+};
+
+template <int WIN, bool ST = false>
+struct StageT : StageExtra<WIN>, StatsExtra<ST> {
     float4 q[kChunks][kBatch];
     float z[kBatch];
     uint16_t hit[kBatch];        // bit 4 w + g: may composite in block g of quadrant w
@@ -204,17 +216,30 @@ __device__ __forceinline__ int per_row(int g, int j0, int j1, int j2, int j3)
     return g == 0 ? j0 : g == 1 ? j1 : g == 2 ? j2 : j3;
 }
 
+// min_k u_k without the arg-min, for the forward: one v_min_f64 per edge
+// instead of a compare and two selects.  The three u_k are the same FMAs as
+// in edge_min, so the minimum is the same double.
+__device__ __forceinline__ double edge_min_value(const double* A, const double* B,
+                                                 const double* C, double dx, double dy)
+{
+    const double u0 = fma(A[0], dx, fma(B[0], dy, C[0]));
+    const double u1 = fma(A[1], dx, fma(B[1], dy, C[1]));
+    const double u2 = fma(A[2], dx, fma(B[2], dy, C[2]));
+    return fmin(fmin(u0, u1), u2);
+}
+
 // Window and opacity of a staged record at the pixel (dx, dy) from the
 // tile's corner.  Returns whether the pixel is in the window's support (the
-// forms of Eq. 1: u > 0; the sigmoid: everywhere).  Forward and backward
-// call exactly this.
-template <int WIN>
+// forms of Eq. 1: u > 0; the sigmoid: everywhere).  Forward (K = false: no
+// arg-min edge) and backward take the same alpha and the same decisions.
+template <int WIN, bool K = true>
 __device__ __forceinline__ bool frag_alpha(const TriRecord& r, double dx, double dy,
                                            float alpha_max, Frag& f)
 {
-    int k;
+    int k = 0;
     if constexpr (WIN == TS_WINDOW_SIGMOID) {
-        const double d = edge_min(r.A, r.B, r.C, dx, dy, k);
+        const double d = K ? edge_min(r.A, r.B, r.C, dx, dy, k)
+                           : edge_min_value(r.A, r.B, r.C, dx, dy);
         sigmoid_alpha(d, r.o, r.sigma, alpha_max, f);
         f.k = k;
         return true;
@@ -223,8 +248,9 @@ __device__ __forceinline__ bool frag_alpha(const TriRecord& r, double dx, double
         window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
         return u > 0.0;
     } else {
-        const double u = edge_min(r.A, r.B, r.C, dx, dy, k);
-        window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
+        const double u = K ? edge_min(r.A, r.B, r.C, dx, dy, k)
+                           : edge_min_value(r.A, r.B, r.C, dx, dy);
+        window_alpha(fmax(u, 0.0), r.o, r.sigma, alpha_max, f);
         f.k = k;
         return u > 0.0;
     }
@@ -289,10 +315,10 @@ struct TileJob {
     uint32_t* pixels;   // and pixels where it is composited
 };
 
-template <int WIN>
+template <int WIN, bool ST>
 __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
                                          const uint32_t* __restrict__ vals, const Cfg& cfg,
-                                         const TileJob& J, StageT<WIN>& S)
+                                         const TileJob& J, StageT<WIN, ST>& S)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const Pix P = pixel_of(J.tx, J.ty);
@@ -312,6 +338,10 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             const uint32_t tri = vals[b + tid];
             S.tri[tid] = tri;
             S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, J.tx * kTile, J.ty * kTile);
+            if constexpr (ST) {
+                S.mw[tid] = 0u;
+                S.px[tid] = 0u;
+            }
         }
         if (tid < kBatch / 2) S.comp[tid] = 0u;
         __syncthreads();
@@ -331,7 +361,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             jn = lst[k + 1 < kBatch ? k + 1 : 0];
             const TriRecord r = read_rec(S, j);
             Frag f;
-            const bool in = frag_alpha<WIN>(r, dxt, dyt, cfg.alpha_max, f);
+            const bool in = frag_alpha<WIN, false>(r, dxt, dyt, cfg.alpha_max, f);
             const bool contrib = act && in && f.a >= cfg.alpha_min;
             const float Tn = T * (1.f - f.a);
             const bool stop = contrib && Tn < cfg.T_min;
@@ -345,23 +375,29 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             T = comp ? Tn : T;
             last = comp ? b - start + (uint32_t)j + 1u : last;
             done = done || stop;
-            if (J.blocks || J.max_weight) {
+            if (ST || J.blocks) {
                 const uint64_t cm = __ballot(comp);
                 const uint32_t rowbits = (uint32_t)(cm >> (16 * P.g)) & 0xffffu;
                 if (J.blocks && P.i == 0 && rowbits != 0u)   // the entry composited in this block
                     atomicOr(&S.comp[jl >> 1], my_bit << (16 * (jl & 1)));
-                if (J.max_weight) {   // pruning statistics of the row's entry
+                if constexpr (ST) {   // pruning statistics of the row's entry, in LDS
                     const float mw = row_max_f(tw);
                     if (P.i == 0 && rowbits != 0u) {
-                        const uint32_t tri = S.tri[jl];
-                        atomicMax(reinterpret_cast<int*>(J.max_weight + tri), __float_as_int(mw));
-                        atomicAdd(J.pixels + tri, (uint32_t)__popc(rowbits));
+                        atomicMax(&S.mw[jl], __float_as_uint(mw));
+                        atomicAdd(&S.px[jl], (uint32_t)__popc(rowbits));
                     }
                 }
             }
         }
         const bool all_done = __syncthreads_and(done);
         if (J.blocks && tid < n) J.blocks[b + tid] = (uint16_t)(S.comp[tid >> 1] >> (16 * (tid & 1)));
+        if constexpr (ST) {
+            if (tid < n && S.px[tid] != 0u) {
+                const uint32_t tri = S.tri[tid];
+                atomicMax(reinterpret_cast<uint32_t*>(J.max_weight) + tri, S.mw[tid]);
+                atomicAdd(J.pixels + tri, S.px[tid]);
+            }
+        }
         if (all_done) break;
     }
     if (inside) {
@@ -377,7 +413,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     }
 }
 
-template <int WIN>
+template <int WIN, bool ST>
 __global__ __launch_bounds__(256) void k_raster_fwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
@@ -386,7 +422,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     uint16_t* __restrict__ out_blocks, float* __restrict__ max_weight,
     uint32_t* __restrict__ pixels)
 {
-    __shared__ StageT<WIN> S;
+    __shared__ StageT<WIN, ST> S;
     const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     if ((unsigned)tile >= (unsigned)num_tiles) return;   // a corrupt order never reads past ranges
     TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
@@ -649,10 +685,17 @@ void launch_raster_forward(const void* rec, const uint32_t* vals, const uint32_t
                            cam, cfg, tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks,
                            max_weight, pixels);
     };
+    const bool st = max_weight != nullptr;
     switch (cfg.window) {
-    case TS_WINDOW_SIGMOID: go(k_raster_fwd<TS_WINDOW_SIGMOID>); break;
-    case TS_WINDOW_LSE: go(k_raster_fwd<TS_WINDOW_LSE>); break;
-    default: go(k_raster_fwd<TS_WINDOW_PAPER>); break;
+    case TS_WINDOW_SIGMOID:
+        st ? go(k_raster_fwd<TS_WINDOW_SIGMOID, true>) : go(k_raster_fwd<TS_WINDOW_SIGMOID, false>);
+        break;
+    case TS_WINDOW_LSE:
+        st ? go(k_raster_fwd<TS_WINDOW_LSE, true>) : go(k_raster_fwd<TS_WINDOW_LSE, false>);
+        break;
+    default:
+        st ? go(k_raster_fwd<TS_WINDOW_PAPER, true>) : go(k_raster_fwd<TS_WINDOW_PAPER, false>);
+        break;
     }
 }
 

@@ -17,6 +17,7 @@ namespace ts {
 constexpr int kS = 16;            // output tile
 constexpr int kR = 5;             // window radius
 constexpr int kP = kS + 2 * kR;   // staged patch width
+constexpr int kPS = 28;           // row stride of a staged patch: whole 16-byte vectors
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
@@ -26,27 +27,55 @@ struct Win11 {
 
 // Row pass then column pass of the separable window over NQ staged
 // quantities: in[q][26][26] -> out[q] at this thread's pixel (ty, tx).
+// Each pass is register-blocked: one thread loads a whole staged row (or
+// column) once and produces its 16 outputs, so LDS reads drop from 11 per
+// output to under 2.
 template <int NQ>
-__device__ __forceinline__ void blur_patch(float (*in)[kP][kP], float (*row)[kP][kS],
-                                           const Win11& W, int tx, int ty, float* out)
+__device__ __forceinline__ void blur_patch(float (*in)[kP][kPS], float (*row)[kP][kS],
+                                           float (*col)[kS][kS], const Win11& W, int tx, int ty,
+                                           float* out)
 {
     const int t = threadIdx.x;
-    // row pass: kP rows x kS columns per quantity
-    for (int e = t; e < NQ * kP * kS; e += 256) {
-        const int q = e / (kP * kS), r = (e / kS) % kP, c = e % kS;
-        float acc = 0.f;
+    if (t < NQ * kP) {   // row job (q, r)
+        const int q = t / kP, r = t - q * kP;
+        float v[kPS];
+        const float4* src = reinterpret_cast<const float4*>(&in[q][r][0]);
 #pragma unroll
-        for (int k = 0; k < 11; ++k) acc = fmaf(W.w[k], in[q][r][c + k], acc);
-        row[q][r][c] = acc;
+        for (int c4 = 0; c4 < kPS / 4; ++c4) {
+            const float4 x = src[c4];
+            v[4 * c4] = x.x; v[4 * c4 + 1] = x.y; v[4 * c4 + 2] = x.z; v[4 * c4 + 3] = x.w;
+        }
+        float4* dst = reinterpret_cast<float4*>(&row[q][r][0]);
+#pragma unroll
+        for (int c4 = 0; c4 < kS / 4; ++c4) {
+            float o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < 11; ++k) acc = fmaf(W.w[k], v[4 * c4 + j + k], acc);
+                o[j] = acc;
+            }
+            dst[c4] = make_float4(o[0], o[1], o[2], o[3]);
+        }
+    }
+    __syncthreads();
+    if (t < NQ * kS) {   // column job (q, c)
+        const int q = t / kS, c = t - q * kS;
+        float v[kP];
+#pragma unroll
+        for (int r = 0; r < kP; ++r) v[r] = row[q][r][c];
+#pragma unroll
+        for (int y = 0; y < kS; ++y) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) acc = fmaf(W.w[k], v[y + k], acc);
+            col[q][y][c] = acc;
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < 11; ++k) acc = fmaf(W.w[k], row[q][ty + k][tx], acc);
-        out[q] = acc;
-    }
+    for (int q = 0; q < NQ; ++q) out[q] = col[q][ty][tx];
 }
 
 // Per pixel and channel: SSIM and the coefficients of its gradient,
@@ -59,8 +88,9 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x_im
                                                   Win11 win, float up, float* __restrict__ coef,
                                                   float* __restrict__ part)
 {
-    __shared__ float in[5][kP][kP];
-    __shared__ float row[5][kP][kS];
+    __shared__ __align__(16) float in[5][kP][kPS];
+    __shared__ __align__(16) float row[5][kP][kS];
+    __shared__ float col[5][kS][kS];
     __shared__ float red[2][8];
     const int ch = blockIdx.z;
     const int64_t hw = (int64_t)W * H;
@@ -81,7 +111,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x_im
     __syncthreads();
     const int tx = threadIdx.x % kS, ty = threadIdx.x / kS;
     float m[5];
-    blur_patch<5>(in, row, win, tx, ty, m);
+    blur_patch<5>(in, row, col, win, tx, ty, m);
     const int px = blockIdx.x * kS + tx, py = blockIdx.y * kS + ty;
     const bool inside = px < W && py < H;
     float l1 = 0.f, s = 0.f;
@@ -127,8 +157,9 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x_im
                                                   const float* __restrict__ coef,
                                                   float* __restrict__ grad)
 {
-    __shared__ float in[3][kP][kP];
-    __shared__ float row[3][kP][kS];
+    __shared__ __align__(16) float in[3][kP][kPS];
+    __shared__ __align__(16) float row[3][kP][kS];
+    __shared__ float col[3][kS][kS];
     const int ch = blockIdx.z;
     const int64_t hw = (int64_t)W * H;
     const float* cc = coef + ch * 3 * hw;
@@ -144,7 +175,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x_im
     __syncthreads();
     const int tx = threadIdx.x % kS, ty = threadIdx.x / kS;
     float b[3];
-    blur_patch<3>(in, row, win, tx, ty, b);
+    blur_patch<3>(in, row, col, win, tx, ty, b);
     const int px = blockIdx.x * kS + tx, py = blockIdx.y * kS + ty;
     if (px >= W || py >= H) return;
     const int64_t p = ch * hw + (int64_t)py * W + px;
