@@ -79,3 +79,42 @@ def test_struct_layouts_match_header():
             assert getattr(ct[s], f).offset == int(v), k
         else:
             assert ctypes.sizeof(ct[k]) == int(v), k
+
+
+def test_argument_checks_need_no_gpu():
+    """Validation errors of the training-side entry points return before any
+    HIP call: TS_EINVAL / TS_EWORKSPACE on the host alone."""
+    assert B.ts_densify_workspace_bytes(10) < B.ts_densify_workspace_bytes(10_000)
+    assert B.ts_image_loss_workspace_bytes(0, 5) == 0
+    assert B.ts_image_loss_workspace_bytes(64, 48) < B.ts_image_loss_workspace_bytes(128, 96)
+    with pytest.raises(B.TSError) as e:
+        B.ts_densify_select(None, None, -1, B.TS_DENSIFY_OPACITY, 1.0, None, None, None, 0)
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_densify_select(None, None, 5, 7, 1.0, None, None, None, 0)
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_densify_select(1, 1, 5, B.TS_DENSIFY_INV_SIGMA, float("nan"), 1, 1, 1, 1 << 20)
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_densify_select(1, 1, 5000, B.TS_DENSIFY_OPACITY, 1.0, 1, 1, 1, 8)
+    assert e.value.code == B.TS_EWORKSPACE
+    with pytest.raises(B.TSError) as e:
+        B.ts_densify_subdivide(1, 1, 1, 1, 3, 10, 5, 1, 1, 1 << 20, 1)
+    assert e.value.code == B.TS_EINVAL                        # capacity below N
+    with pytest.raises(B.TSError) as e:
+        B.ts_image_loss(1, 1, 0, 8, 0.2, 1, None, 1, 1 << 20)
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_image_loss(1, 1, 8, 8, 1.5, 1, None, 1, 1 << 20)
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_image_loss(1, 1, 64, 64, 0.2, 1, None, 1, 16)
+    assert e.value.code == B.TS_EWORKSPACE
+    st = B.ts_adam_state(*([1] * 8))
+    with pytest.raises(B.TSError) as e:
+        B.ts_optimizer_step(1, 1, 1, 1, 1, 1, 3, 10, 1, 1, 1, 1, st, B.ts_optimizer(step=0))
+    assert e.value.code == B.TS_EINVAL
+    with pytest.raises(B.TSError) as e:
+        B.ts_optimizer_step(1, 1, 1, 1, 1, 1, 4, 10, 1, 1, 1, 1, st, B.ts_optimizer(step=1))
+    assert e.value.code == B.TS_EINVAL

@@ -99,3 +99,41 @@ def test_window_out_of_range_is_rejected():
     with pytest.raises(B.TSError) as e:
         B.ts_project(*sct, sc.n, B.make_camera(cam), bad, st.proj)
     assert e.value.code == B.TS_EINVAL
+
+
+@pytest.mark.parametrize("window", WINDOWS, ids=[NAMES[w] for w in WINDOWS])
+def test_batched_serving_equals_alone(window):
+    """The batched multi-view forward (graph replays of one persistent launch)
+    with an alternative window: each view equals the same view rendered
+    alone, bit for bit."""
+    import time
+    import torch
+    from paper_2505_19175_amd.render import Rasterizer, ViewState, scene_to_device
+    from paper_2505_19175_amd.serve.executor import BatchedExecutor
+    from paper_2505_19175_amd.serve.scheduler import Request
+    rng = np.random.Generator(np.random.PCG64(78))
+    sc = synth.cluster_soup(78, 20_000, extent=3.0, std=0.4, edge_median=0.06, sh_degree=3,
+                            rng=rng)
+    cfg = synth.Config(sh_degree=3, window=window)
+    st = scene_to_device(sc, "cuda:0")
+    eyes = synth.hemisphere_eyes(np.random.Generator(np.random.PCG64(3)), 3)
+    cams = [synth.look_at(e, width=w, height=h) for e, (w, h) in
+            zip(eyes, [(320, 200), (640, 360), (333, 177)])]
+    alone = []
+    for c in cams:
+        s = ViewState(sc.n, c.width, c.height, 1 << 21)
+        out = Rasterizer(cfg).forward(s, st, c, sync=True)
+        torch.cuda.synchronize()
+        alone.append((out.rgb.cpu().numpy(), out.alpha.cpu().numpy()))
+    ex = BatchedExecutor(st, cfg, time.perf_counter, max_views=3, max_tiles=3 * 920,
+                         max_pixels=3 * 640 * 360, capacity=1 << 22, slots=1)
+    batch = [Request(i, c, 0.0) for i, c in enumerate(cams)]
+    ex.submit(0, batch)
+    while True:
+        res = ex.poll(0)
+        if res is not None:
+            break
+    assert not res.overflow and res.instances > 0
+    for (rgb, a, d), (want_rgb, want_a) in zip(ex.outputs(0, batch), alone):
+        np.testing.assert_array_equal(rgb.cpu().numpy(), want_rgb)
+        np.testing.assert_array_equal(a.cpu().numpy(), want_a)
