@@ -71,10 +71,13 @@ class TrainState:
                         torch.cuda.current_stream().cuda_stream)
         return self.dC
 
-    def step(self, ras: Rasterizer, st: ViewState, cam, target, sync: bool = False) -> Outputs:
-        """forward -> image loss -> backward -> regularizers + Adam."""
+    def step(self, ras: Rasterizer, st: ViewState, cam, target, sync: bool = False,
+             stats=None) -> Outputs:
+        """forward -> image loss -> backward -> regularizers + Adam.  With
+        stats (render.PruneStats) the forward also keeps the pruning
+        statistics of the view."""
         stream = torch.cuda.current_stream().cuda_stream
-        out = ras.forward(st, self.scene_t(), cam, sync=sync)
+        out = ras.forward(st, self.scene_t(), cam, sync=sync, stats=stats)
         dC = self.image_loss(out.rgb, target)
         gv, go, gs, gsh = self.grads
         B.ts_render_backward(self.v, self.o, self.sigma, self.sh, self.N, st.proj, st.bins,

@@ -145,9 +145,15 @@ def test_fit_lowers_the_loss():
     ts = TrainState(sc, device=DEV, lr_v=0.003)
     st = ViewState(sc.n, cam.width, cam.height, 1 << 16, device=DEV)
     losses = []
+    from paper_2505_19175_amd.render import PruneStats
+    ps = PruneStats(sc.n, device=DEV)
     for k in range(40):
-        ts.step(ras, st, cam, target, sync=True)
+        ts.step(ras, st, cam, target, sync=True, stats=ps if k >= 38 else None)
         torch.cuda.synchronize()
         losses.append(ts.loss_value())
     assert losses[-1] < 0.85 * losses[0], losses
     assert np.isfinite(losses).all()
+    # the last two steps kept the pruning statistics of their forward
+    views = ps.views.cpu().numpy()
+    assert views.max() == 2 and (views == 2).sum() > 100
+    assert 0.0 < float(ps.max_weight.max()) <= 1.0
