@@ -16,14 +16,20 @@
  *     drops the rim where o*I < tau_cutoff                         (Supp., "Tile assignment")
  *   - the depth order is that of the triangle centres             (Supp., "Depth sorting")
  *   - SH colour up to degree 3, 59 parameters per triangle        (Sec. 4, "Implementation details")
+ * and, around that path, what a training step needs: the two window
+ * alternatives the paper discusses (Sec. 3.1; Eq. 2), the pruning
+ * statistics (Sec. 3.2, "Pruning"), the densification sampling and midpoint
+ * subdivision (Sec. 3.2, "Densification"), the photometric loss with its
+ * regularizers and Adam (Sec. 3.3).
  *
  * Conventions fixed by this library where the paper is silent:
  *   - camera: x_c = R v + t with OpenCV axes (x right, y down, z forward);
  *     q = (fx x_c/z_c + cx, fy y_c/z_c + cy); pixel (i,j) is sampled at its
  *     centre (i+1/2, j+1/2)
  *   - a triangle is dropped if any vertex has z_c <= z_near, if its 2D
- *     inradius is below r_min, if o < alpha_min, or if its tight box holds
- *     no pixel centre; no back-face culling
+ *     inradius is below r_min, if o < alpha_min (o <= alpha_min for the
+ *     sigmoid window), or if its tight box holds no pixel centre; no
+ *     back-face culling
  *   - alpha = min(alpha_max, o*I); a fragment with alpha < alpha_min is
  *     skipped; one whose T(1-alpha) would fall below T_min ends the pixel
  *   - depth key = float32 of the mean camera-space z of the three vertices,
@@ -38,7 +44,8 @@
  * and h_count is a DEVICE pointer owned by the caller; the library never
  * allocates or frees.  Buffers are row-major and contiguous; images are
  * planar [C][H][W] float32.  All calls are asynchronous on `stream`; only
- * ts_bin_sort with a non-NULL h_count synchronises it.
+ * ts_bin_sort and ts_densify_subdivide with a non-NULL h_count synchronise
+ * it.
  *
  * Errors: every entry point returns TS_OK (0) or a TS_E* code and launches
  * nothing on a validation error.  TS_EHIP wraps a failed HIP launch (the HIP
