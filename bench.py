@@ -409,7 +409,7 @@ def main():
                          for k in range(reps)]).mean(0)
         ms_t = max(float(evt[0][0].elapsed_time(evt[-1][4])) / reps, wall_t)
         K3 = 3 * K
-        opt_bytes = N * (28.0 * (9 + 2 + K3) + 132.0)
+        opt_bytes = N * (28.0 * (9 + K3) + 2 * 36.0)
         loss_bytes = 44.0 * 3 * W * H
         res["train_step"] = {
             "workload": f"tri3M_{W}x{H}: fit a copy of the soup with vertices moved by "
@@ -422,8 +422,9 @@ def main():
             "image_loss_GBps_algorithmic": round(loss_bytes / (part[1] * 1e-3) / 1e9, 1),
             "optimizer_GBps_algorithmic": round(opt_bytes / (part[3] * 1e-3) / 1e9, 1),
             "loss_first": round(loss0, 6), "loss_last": round(ts.loss_value(), 6),
-            "bytes_note": "optimizer: 28 B per parameter (read p, g, m, s; write p, m, s) + "
-                          "132 B per triangle for the regularizers; image loss: 44 B per value"}
+            "bytes_note": "optimizer: 28 B per parameter (read p, g, m, s; write p, m, s), 36 B "
+                          "for the opacity and sigma logits (their activated copies read and "
+                          "rewritten); image loss: 44 B per value"}
         del ts, stt, outt, tgt
     if not args.no_densify:
         # densification (Sec. 3.2) on the same soup: Bernoulli selection of

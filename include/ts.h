@@ -395,8 +395,7 @@ int ts_densify_subdivide(float* v, float* o, float* sigma, float* sh, int sh_deg
  *   v [N][3][3], a, b [N], sh [N][(deg+1)^2][3]: raw parameters (device)
  *   o, sigma [N]: their activated copies (read, then rewritten)
  *   gv, go, gsigma, gsh: the renderer's gradients w.r.t. v, o, sigma, sh
- *                (as ts_render_backward writes them); go and gsigma are
- *                overwritten with the gradients w.r.t. a and b
+ *                (as ts_render_backward writes them); read only
  *   state: the first and second moment arrays, shaped like the parameters,
  *                zero before the first step
  *   opt: learning rates, Adam constants, loss weights and the step number

@@ -389,19 +389,16 @@ int ts_optimizer_step(float* v, float* a, float* b, float* sh, float* o, float* 
     if (!v || !a || !b || !sh || !o || !sigma || !gv || !go || !gsigma || !gsh || !st->m_v ||
         !st->s_v || !st->m_a || !st->s_a || !st->m_b || !st->s_b || !st->m_sh || !st->s_sh)
         return fail(TS_EINVAL, "ts_optimizer_step: null pointer");
-    ts::launch_train_reg(v, o, sigma, N, opt->beta_opacity, opt->beta_size, gv, go, gsigma, stream);
     const float bc1 = (float)(1.0 - pow((double)opt->beta1, opt->step));
     const float bc2 = (float)(1.0 - pow((double)opt->beta2, opt->step));
-    const int K3 = 3 * (sh_degree + 1) * (sh_degree + 1);
-    ts::launch_adam(v, gv, st->m_v, st->s_v, 9 * N, 9, 9, opt->lr_v, opt->lr_v, opt->beta1,
-                    opt->beta2, bc1, bc2, opt->eps, 0, nullptr, stream);
-    ts::launch_adam(a, go, st->m_a, st->s_a, N, 1, 1, opt->lr_opacity, opt->lr_opacity,
-                    opt->beta1, opt->beta2, bc1, bc2, opt->eps, 1, o, stream);
-    ts::launch_adam(b, gsigma, st->m_b, st->s_b, N, 1, 1, opt->lr_sigma, opt->lr_sigma,
-                    opt->beta1, opt->beta2, bc1, bc2, opt->eps, 2, sigma, stream);
-    ts::launch_adam(sh, gsh, st->m_sh, st->s_sh, (int64_t)K3 * N, K3, 3, opt->lr_sh_dc,
-                    opt->lr_sh_rest, opt->beta1, opt->beta2, bc1, bc2, opt->eps, 0, nullptr,
-                    stream);
+    const int nsh = 3 * (sh_degree + 1) * (sh_degree + 1);
+    float* const state[8] = {st->m_v, st->s_v, st->m_a, st->s_a, st->m_b, st->s_b, st->m_sh,
+                             st->s_sh};
+    const float lr[5] = {opt->lr_v, opt->lr_opacity, opt->lr_sigma, opt->lr_sh_dc,
+                         opt->lr_sh_rest};
+    ts::launch_optimizer(v, a, b, sh, o, sigma, nsh, N, gv, go, gsigma, gsh, state, lr,
+                         opt->beta_opacity, opt->beta_size, opt->beta1, opt->beta2, bc1, bc2,
+                         opt->eps, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_optimizer_step");
 }

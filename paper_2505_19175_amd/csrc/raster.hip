@@ -41,20 +41,15 @@ struct StageExtra<TS_WINDOW_LSE> {
     float ps[kBatch];
 };
 
-// Per-entry pruning statistics of a batch (the forward that keeps them
-// only): largest T*o (float bits; non-negative floats order as integers)
-// and composited pixels over the tile, flushed with one global atomic pair
-// per entry at the end of the batch.
-template <bool ST>
-struct StatsExtra {};
-template <>
-struct StatsExtra<true> {
-    uint32_t mw[kBatch];
-    uint32_t px[kBatch];
-};
-
+// The forward that keeps pruning statistics gathers them per batch entry in
+// words the plain forward does not need during its walk, so its LDS stays at
+// 25 allocation units: the largest T*o (float bits; non-negative floats
+// order as integers) in the triangle-index words, the composited pixels as
+// 16-bit halves of the per-entry block-hit words (dead once every wave has
+// built its lists).  One global max and one add per entry and tile flush
+// them at the end of the batch.
 template <int WIN, bool ST = false>
-struct StageT : StageExtra<WIN>, StatsExtra<ST> {
+struct StageT : StageExtra<WIN> {
     float4 q[kChunks][kBatch];
     float z[kBatch];
     uint16_t hit[kBatch];        // bit 4 w + g: may composite in block g of quadrant w
@@ -336,16 +331,18 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         __syncthreads();
         if (tid < n) {
             const uint32_t tri = vals[b + tid];
-            S.tri[tid] = tri;
+            S.tri[tid] = ST ? 0u : tri;   // the statistics' max-weight word
             S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, J.tx * kTile, J.ty * kTile);
-            if constexpr (ST) {
-                S.mw[tid] = 0u;
-                S.px[tid] = 0u;
-            }
         }
         if (tid < kBatch / 2) S.comp[tid] = 0u;
         __syncthreads();
         const Lens L = build_lists(S, n, P.w, lane, n, n, n, n);
+        uint32_t* px = reinterpret_cast<uint32_t*>(S.hit);   // 16 bits per entry
+        if constexpr (ST) {   // the hit words are dead once every wave has its lists
+            __syncthreads();
+            if (tid < kBatch / 2) px[tid] = 0u;
+            __syncthreads();
+        }
         // each lane walks its row's list; a row stops once all its pixels are
         // done, the wave once no row has work left
         const int len = per_row(P.g, L.n0, L.n1, L.n2, L.n3);
@@ -383,8 +380,8 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
                 if constexpr (ST) {   // pruning statistics of the row's entry, in LDS
                     const float mw = row_max_f(tw);
                     if (P.i == 0 && rowbits != 0u) {
-                        atomicMax(&S.mw[jl], __float_as_uint(mw));
-                        atomicAdd(&S.px[jl], (uint32_t)__popc(rowbits));
+                        atomicMax(&S.tri[jl], __float_as_uint(mw));
+                        atomicAdd(&px[jl >> 1], (uint32_t)__popc(rowbits) << (16 * (jl & 1)));
                     }
                 }
             }
@@ -392,10 +389,10 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         const bool all_done = __syncthreads_and(done);
         if (J.blocks && tid < n) J.blocks[b + tid] = (uint16_t)(S.comp[tid >> 1] >> (16 * (tid & 1)));
         if constexpr (ST) {
-            if (tid < n && S.px[tid] != 0u) {
-                const uint32_t tri = S.tri[tid];
-                atomicMax(reinterpret_cast<uint32_t*>(J.max_weight) + tri, S.mw[tid]);
-                atomicAdd(J.pixels + tri, S.px[tid]);
+            if (tid < n && S.tri[tid] != 0u) {
+                const uint32_t tri = vals[b + tid];
+                atomicMax(reinterpret_cast<uint32_t*>(J.max_weight) + tri, S.tri[tid]);
+                atomicAdd(J.pixels + tri, (px[tid >> 1] >> (16 * (tid & 1))) & 0xffffu);
             }
         }
         if (all_done) break;

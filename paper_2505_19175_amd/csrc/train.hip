@@ -150,16 +150,55 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ x_im
     }
 }
 
+// loss[0] = mean |x - y|, loss[1] = mean SSIM, from the per-workgroup sums
+// (one workgroup, fixed order: reproducible).  s holds 2 x 256 doubles.
+__device__ void loss_total(const float* __restrict__ part, int64_t nb, double n,
+                           float* __restrict__ loss, double (*s)[256])
+{
+    double a = 0.0, b = 0.0;
+    for (int64_t j = threadIdx.x; j < nb; j += 256) {
+        a += part[2 * j];
+        b += part[2 * j + 1];
+    }
+    s[0][threadIdx.x] = a;
+    s[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + h];
+            s[1][threadIdx.x] += s[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss[0] = (float)(s[0][0] / n);
+        loss[1] = (float)(s[1][0] / n);
+    }
+}
+
 // dL/dC = (1 - lambda) sign(x - y) / n + blur(d_mx) + 2 x blur(d_exx) + y blur(d_exy).
+// With loss set, the grid has a fourth z-plane whose first workgroup sums
+// the forward's partial sums into the loss value (the other workgroups of
+// that plane exit): the reduction runs beside the gradient tiles instead of
+// in a launch of its own.
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x_img,
                                                   const float* __restrict__ y_img, int W, int H,
                                                   Win11 win, float l1w,
                                                   const float* __restrict__ coef,
-                                                  float* __restrict__ grad)
+                                                  float* __restrict__ grad,
+                                                  const float* __restrict__ part, double n,
+                                                  float* __restrict__ loss)
 {
     __shared__ __align__(16) float in[3][kP][kPS];
     __shared__ __align__(16) float row[3][kP][kS];
     __shared__ float col[3][kS][kS];
+    static_assert(sizeof(in) >= 2 * 256 * sizeof(double), "reduction scratch");
+    if (blockIdx.z == 3) {
+        if (blockIdx.x == 0 && blockIdx.y == 0)
+            loss_total(part, (int64_t)gridDim.x * gridDim.y * 3, n, loss,
+                       reinterpret_cast<double (*)[256]>(&in[0][0][0]));
+        return;
+    }
     const int ch = blockIdx.z;
     const int64_t hw = (int64_t)W * H;
     const float* cc = coef + ch * 3 * hw;
@@ -182,33 +221,6 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ x_im
     const float x = x_img[p], y = y_img[p];
     const float sg = x > y ? 1.f : (x < y ? -1.f : 0.f);
     grad[p] = fmaf(l1w, sg, b[0] + 2.f * x * b[1] + y * b[2]);
-}
-
-// loss[0] = mean |x - y|, loss[1] = mean SSIM, from the per-workgroup sums
-// (one workgroup, fixed order: reproducible).
-__global__ __launch_bounds__(256) void k_loss_total(const float* __restrict__ part, int64_t nb,
-                                                    double n, float* __restrict__ loss)
-{
-    __shared__ double s[2][256];
-    double a = 0.0, b = 0.0;
-    for (int64_t j = threadIdx.x; j < nb; j += 256) {
-        a += part[2 * j];
-        b += part[2 * j + 1];
-    }
-    s[0][threadIdx.x] = a;
-    s[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            s[0][threadIdx.x] += s[0][threadIdx.x + h];
-            s[1][threadIdx.x] += s[1][threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        loss[0] = (float)(s[0][0] / n);
-        loss[1] = (float)(s[1][0] / n);
-    }
 }
 
 size_t image_loss_workspace_bytes(int W, int H)
@@ -234,96 +246,131 @@ void launch_image_loss(const float* rgb, const float* target, int W, int H, floa
     float* part = coef + 9 * (int64_t)W * H;
     hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, stream, rgb, target, W, H, win,
                        (float)(-lambda / n), coef, part);
-    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, stream, rgb, target, W, H, win,
-                       (float)((1.0 - lambda) / n), coef, grad);
-    if (loss)
-        hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, stream, part,
-                           (int64_t)grid.x * grid.y * grid.z, n, loss);
+    const dim3 grid_b(grid.x, grid.y, loss ? 4 : 3);
+    hipLaunchKernelGGL(k_ssim_bwd, grid_b, dim3(256), 0, stream, rgb, target, W, H, win,
+                       (float)((1.0 - lambda) / n), coef, grad, part, n, loss);
 }
 
 // ---------------------------------------------------------------------------
-// Regularizers and the chain through the activations, per triangle:
-//   gv += beta_s d/dv mean 2/|c|, c = (v1 - v0) x (v2 - v0)
-//   ga = (go + beta_o / N) o (1 - o)      (o = sigmoid(a))
-//   gb = gsigma sigma                     (sigma = exp(b))
-// go and gsigma are overwritten with ga and gb.
+// Adam with the regularizers and the activation chain folded in.
+//
+// Vertices, one triangle per thread: g = gv + beta_s d/dv mean 2/|c|,
+// c = (v1 - v0) x (v2 - v0), then the update of its nine coordinates.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_train_reg(const float* __restrict__ v,
-                                                   const float* __restrict__ o,
-                                                   const float* __restrict__ sigma, int64_t N,
-                                                   float beta_o, float beta_s,
-                                                   float* __restrict__ gv, float* __restrict__ go,
-                                                   float* __restrict__ gs)
+struct AdamK {
+    float b1, b2, bc1, bc2, eps;
+};
+
+__device__ __forceinline__ float adam_update(float p, float g, float& m, float& s, float lr,
+                                             const AdamK& k)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
-    float p[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) p[a] = v[9 * i + a];
-    const float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
-    const float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
-    const float c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                        e1[0] * e2[1] - e1[1] * e2[0]};
-    const float n2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-    const float inv = rsqrtf(n2);
-    const float k = -2.f * beta_s / (float)N * inv * inv * inv;   // dL/dc = k c
-    const float gc[3] = {k * c[0], k * c[1], k * c[2]};
-    // c = e1 x e2: dL/de1 = e2 x gc, dL/de2 = gc x e1
-    const float g1[3] = {e2[1] * gc[2] - e2[2] * gc[1], e2[2] * gc[0] - e2[0] * gc[2],
-                         e2[0] * gc[1] - e2[1] * gc[0]};
-    const float g2[3] = {gc[1] * e1[2] - gc[2] * e1[1], gc[2] * e1[0] - gc[0] * e1[2],
-                         gc[0] * e1[1] - gc[1] * e1[0]};
-    const bool ok = n2 > 0.f && beta_s != 0.f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float d1 = ok ? g1[a] : 0.f, d2 = ok ? g2[a] : 0.f;
-        gv[9 * i + a] -= d1 + d2;
-        gv[9 * i + 3 + a] += d1;
-        gv[9 * i + 6 + a] += d2;
-    }
-    const float oi = o[i];
-    go[i] = (go[i] + beta_o / (float)N) * oi * (1.f - oi);
-    gs[i] = gs[i] * sigma[i];
+    m = fmaf(k.b1, m, (1.f - k.b1) * g);
+    s = fmaf(k.b2, s, (1.f - k.b2) * g * g);
+    return p - lr * (m / k.bc1) / (sqrtf(s / k.bc2) + k.eps);
 }
 
-// Bias-corrected Adam over a flat array; element e uses lr_a when
-// e % row < first, else lr_b.  act 1 / 2 writes sigmoid / exp of the new
-// value to out (the renderer's activated copy).
+// The block's 256 vertex and gradient rows are staged through LDS so every
+// global access is coalesced; each thread adds its triangle's size-loss
+// gradient in LDS, then the update runs element-wise.
+__global__ __launch_bounds__(256) void k_adam_vertices(float* __restrict__ v,
+                                                       const float* __restrict__ gv,
+                                                       float* __restrict__ m, float* __restrict__ s,
+                                                       int64_t N, float beta_s, float lr, AdamK k)
+{
+    __shared__ float sv[256 * 9], sg[256 * 9];
+    const int64_t base = (int64_t)blockIdx.x * 256;
+    const int nt = (int)min((int64_t)256, N - base);
+    const int n = 9 * nt;
+    const int64_t off = 9 * base;
+    for (int f = threadIdx.x; f < n; f += 256) {
+        sv[f] = v[off + f];
+        sg[f] = gv[off + f];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < nt && beta_s != 0.f) {
+        const float* p = sv + 9 * t;
+        float* g = sg + 9 * t;
+        const float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+        const float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
+        const float c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                            e1[0] * e2[1] - e1[1] * e2[0]};
+        const float n2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        if (n2 > 0.f) {
+            const float inv = rsqrtf(n2);
+            const float kk = -2.f * beta_s / (float)N * inv * inv * inv;   // dL/dc = kk c
+            const float gc[3] = {kk * c[0], kk * c[1], kk * c[2]};
+            // c = e1 x e2: dL/de1 = e2 x gc, dL/de2 = gc x e1
+            const float g1[3] = {e2[1] * gc[2] - e2[2] * gc[1], e2[2] * gc[0] - e2[0] * gc[2],
+                                 e2[0] * gc[1] - e2[1] * gc[0]};
+            const float g2[3] = {gc[1] * e1[2] - gc[2] * e1[1], gc[2] * e1[0] - gc[0] * e1[2],
+                                 gc[0] * e1[1] - gc[1] * e1[0]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                g[a] -= g1[a] + g2[a];
+                g[3 + a] += g1[a];
+                g[6 + a] += g2[a];
+            }
+        }
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < n; f += 256) {
+        float mi = m[off + f], si = s[off + f];
+        v[off + f] = adam_update(sv[f], sg[f], mi, si, lr, k);
+        m[off + f] = mi;
+        s[off + f] = si;
+    }
+}
+
+// Flat Adam; element e uses lr_a when e % row < first, else lr_b.
+//   act 0: g as given
+//   act 1: opacity logit: g = (g + add) y (1 - y), y = out[e] = sigmoid of the
+//          old value; out[e] becomes sigmoid of the new one
+//   act 2: log sigma: g = g y, y = out[e] = exp of the old value; out[e]
+//          becomes exp of the new one
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ s,
                                               int64_t n, int row, int first, float lr_a, float lr_b,
-                                              float b1, float b2, float bc1, float bc2, float eps,
-                                              int act, float* __restrict__ out)
+                                              AdamK k, int act, float add,
+                                              float* __restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
-    const float gi = g[e];
-    const float mi = fmaf(b1, m[e], (1.f - b1) * gi);
-    const float si = fmaf(b2, s[e], (1.f - b2) * gi * gi);
+    float gi = g[e];
+    if (act == 1) {
+        const float y = out[e];
+        gi = (gi + add) * y * (1.f - y);
+    } else if (act == 2) {
+        gi *= out[e];
+    }
+    float mi = m[e], si = s[e];
+    const float lr = (int)(e % row) < first ? lr_a : lr_b;
+    const float pi = adam_update(p[e], gi, mi, si, lr, k);
     m[e] = mi;
     s[e] = si;
-    const float lr = (int)(e % row) < first ? lr_a : lr_b;
-    const float pi = p[e] - lr * (mi / bc1) / (sqrtf(si / bc2) + eps);
     p[e] = pi;
     if (act == 1) out[e] = 1.f / (1.f + expf(-pi));
     else if (act == 2) out[e] = expf(pi);
 }
 
-void launch_train_reg(const float* v, const float* o, const float* sigma, int64_t N, float beta_o,
-                      float beta_s, float* gv, float* go, float* gs, hipStream_t stream)
+void launch_optimizer(float* v, float* a, float* b, float* sh, float* o, float* sigma, int nsh,
+                      int64_t N, const float* gv, const float* go, const float* gs,
+                      const float* gsh, float* const* st, const float* lr, float beta_o,
+                      float beta_s, float b1, float b2, float bc1, float bc2, float eps,
+                      hipStream_t stream)
 {
-    if (N > 0)
-        hipLaunchKernelGGL(k_train_reg, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, v,
-                           o, sigma, N, beta_o, beta_s, gv, go, gs);
-}
-
-void launch_adam(float* p, const float* g, float* m, float* s, int64_t n, int row, int first,
-                 float lr_a, float lr_b, float b1, float b2, float bc1, float bc2, float eps,
-                 int act, float* out, hipStream_t stream)
-{
-    if (n > 0)
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, g,
-                           m, s, n, row, first, lr_a, lr_b, b1, b2, bc1, bc2, eps, act, out);
+    if (N <= 0) return;
+    const AdamK k{b1, b2, bc1, bc2, eps};
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_adam_vertices, dim3(nb), dim3(256), 0, stream, v, gv, st[0], st[1], N,
+                       beta_s, lr[0], k);
+    hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, stream, a, go, st[2], st[3], N, 1, 1,
+                       lr[1], lr[1], k, 1, beta_o / (float)N, o);
+    hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, stream, b, gs, st[4], st[5], N, 1, 1,
+                       lr[2], lr[2], k, 2, 0.f, sigma);
+    const int64_t n = (int64_t)nsh * N;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, sh, gsh,
+                       st[6], st[7], n, nsh, 3, lr[3], lr[4], k, 0, 0.f, nullptr);
 }
 
 }  // namespace ts

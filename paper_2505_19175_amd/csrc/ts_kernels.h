@@ -106,11 +106,12 @@ void launch_densify_subdivide(float* v, float* o, float* sigma, float* sh, int n
 size_t image_loss_workspace_bytes(int W, int H);
 void launch_image_loss(const float* rgb, const float* target, int W, int H, float lambda,
                        float* grad, float* loss, void* ws, hipStream_t stream);
-void launch_train_reg(const float* v, const float* o, const float* sigma, int64_t N, float beta_o,
-                      float beta_s, float* gv, float* go, float* gs, hipStream_t stream);
-void launch_adam(float* p, const float* g, float* m, float* s, int64_t n, int row, int first,
-                 float lr_a, float lr_b, float b1, float b2, float bc1, float bc2, float eps,
-                 int act, float* out, hipStream_t stream);
+// st: m_v, s_v, m_a, s_a, m_b, s_b, m_sh, s_sh; lr: v, opacity, sigma, SH dc, SH rest.
+void launch_optimizer(float* v, float* a, float* b, float* sh, float* o, float* sigma, int nsh,
+                      int64_t N, const float* gv, const float* go, const float* gs,
+                      const float* gsh, float* const* st, const float* lr, float beta_o,
+                      float beta_s, float b1, float b2, float bc1, float bc2, float eps,
+                      hipStream_t stream);
 
 // views[i] += pixels[i] > 1; pixels[i] = 0.
 void launch_prune_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream);
