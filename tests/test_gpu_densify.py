@@ -96,7 +96,7 @@ def _soup(seed, N, deg):
     return v, o, s, sh
 
 
-@pytest.mark.parametrize("N,deg", [(1, 0), (300, 1), (5000, 3)])
+@pytest.mark.parametrize("N,deg", [(1, 0), (300, 1), (777, 2), (5000, 3)])
 def test_subdivide_bit_exact(N, deg):
     v, o, s, sh = _soup(11, N, deg)
     sel = np.random.default_rng(12).random(N) < 0.3
