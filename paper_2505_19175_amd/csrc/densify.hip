@@ -76,38 +76,46 @@ __global__ __launch_bounds__(kDensBlock) void k_count_sel(const uint8_t* __restr
     if (threadIdx.x == 0) cnt[blockIdx.x] = (uint32_t)c;
 }
 
-// Exclusive scan of the per-workgroup counts by one workgroup, sequential
-// chunks per thread; out[0] = N + 3 n (the new count), out[1] = 1 when that
-// exceeds the capacity (then nothing is written).
-__global__ __launch_bounds__(kDensBlock) void k_scan_sel(uint32_t* __restrict__ cnt, int64_t nb,
-                                                         int64_t N, int64_t capacity,
-                                                         uint32_t* __restrict__ out)
+// Exclusive scan of the per-workgroup counts by one workgroup of 1024
+// threads, 1024 counts per round (coalesced loads, wave scans by shuffles,
+// one LDS exchange of the 16 wave sums); out[0] = N + 3 n (the new count),
+// out[1] = 1 when that exceeds the capacity (then nothing is written).
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sel(uint32_t* __restrict__ cnt,
+                                                           int64_t nb, int64_t N,
+                                                           int64_t capacity,
+                                                           uint32_t* __restrict__ out)
 {
-    __shared__ uint64_t s[kDensBlock];
-    const int t = threadIdx.x;
-    const int64_t per = (nb + kDensBlock - 1) / kDensBlock;
-    const int64_t lo = min(nb, t * per), hi = min(nb, lo + per);
-    uint64_t acc = 0;
-    for (int64_t j = lo; j < hi; ++j) acc += cnt[j];
-    // inclusive scan of the 256 chunk sums (log-step, two barriers a step)
-    s[t] = acc;
-    __syncthreads();
-    for (int off = 1; off < kDensBlock; off <<= 1) {
-        const uint64_t x = t >= off ? s[t - off] : 0;
+    __shared__ uint32_t ws[kScanThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    uint64_t run = 0;   // the same in every thread
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        const int64_t j = base + t;
+        const uint32_t x = j < nb ? cnt[j] : 0u;
+        uint32_t v = x;   // inclusive scan over the wave
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(v, o);
+            v += lane >= o ? y : 0u;
+        }
+        if (lane == kWave - 1) ws[w] = v;
         __syncthreads();
-        s[t] += x;
-        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < kScanThreads / kWave; ++k) {
+            const uint32_t sk = ws[k];
+            before += k < w ? sk : 0u;
+            tot += sk;
+        }
+        if (j < nb) cnt[j] = (uint32_t)(run + before + v - x);
+        run += tot;
+        __syncthreads();   // the wave sums are rewritten next round
     }
-    if (t == kDensBlock - 1) {
-        const uint64_t total = (uint64_t)N + 3 * s[t];
+    if (t == 0) {
+        const uint64_t total = (uint64_t)N + 3 * run;
         out[0] = (uint32_t)min(total, (uint64_t)0xffffffffu);
         out[1] = total > (uint64_t)capacity ? 1u : 0u;
-    }
-    uint64_t run = s[t] - acc;
-    for (int64_t j = lo; j < hi; ++j) {
-        const uint32_t x = cnt[j];
-        cnt[j] = (uint32_t)run;
-        run += x;
     }
 }
 
@@ -216,7 +224,7 @@ void launch_densify_subdivide(float* v, float* o, float* sigma, float* sh, int n
     const int64_t nb = (N + kDensBlock - 1) / kDensBlock;
     uint32_t* cnt = reinterpret_cast<uint32_t*>(ws);
     hipLaunchKernelGGL(k_count_sel, dim3((unsigned)nb), dim3(kDensBlock), 0, stream, sel, N, cnt);
-    hipLaunchKernelGGL(k_scan_sel, dim3(1), dim3(kDensBlock), 0, stream, cnt, nb, N, capacity,
+    hipLaunchKernelGGL(k_scan_sel, dim3(1), dim3(kScanThreads), 0, stream, cnt, nb, N, capacity,
                        d_out);
     hipLaunchKernelGGL(k_subdivide, dim3((unsigned)nb), dim3(kDensBlock), 0, stream, v, o, sigma,
                        sh, nsh, N, sel, cnt, d_out);
