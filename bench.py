@@ -122,6 +122,65 @@ def cpu_baseline(wl, cam, n_pix, seed=2024):
     return res, float(np.mean(ref["nfrag"]))
 
 
+def cpu_rows(wl, cam, cfg_windows, img, soup_slice=300_000, seed=2025):
+    """The oracle beside each path beyond the step, on bounded samples of the
+    same workload (about 20 s of host time in all): the statistics and the
+    two windows on seeded pixel samples, the image loss on the whole frame,
+    Adam on a slice of the soup, densification on the whole soup."""
+    import numpy as np
+
+    from oracle import densify as OD
+    from oracle import oracle as O
+    from oracle import train as OT
+    from paper_2505_19175_amd import synth
+    out = {}
+    cores = O.threads()
+    pix = synth.pixel_sample(seed, cam.width, cam.height, 256)
+    t0 = time.perf_counter()
+    O.prune_stats(wl.scene, cam, wl.config, pix=pix)
+    dt = time.perf_counter() - t0
+    out["prune_stats"] = {"value": round(256 / dt / 1e6, 6), "unit": "Mpixel/s", "cores": cores,
+                          "kind": "oracle", "sample": f"256 seeded pixels, {dt:.1f} s"}
+    dC, _, _ = synth.upstream(seed + 1, cam.width, cam.height)
+    for name, cfg_w in cfg_windows.items():
+        pw = pix[:128]
+        t0 = time.perf_counter()
+        O.render(wl.scene, cam, cfg_w, pix=pw)
+        O.backward(wl.scene, cam, cfg_w, dC.reshape(3, -1)[:, pw], pix=pw)
+        dt = time.perf_counter() - t0
+        out[f"window_{name}"] = {"value": round(128 / dt / 1e6, 6), "unit": "Mpixel/s",
+                                 "cores": cores, "kind": "oracle",
+                                 "sample": f"128 seeded pixels, forward + backward, {dt:.1f} s"}
+    rng = np.random.default_rng(seed)
+    tgt = np.clip(img + rng.normal(0, 0.05, img.shape), 0, 1)
+    t0 = time.perf_counter()
+    OT.image_loss_grad(img, tgt)
+    dt = time.perf_counter() - t0
+    out["image_loss"] = {"value": round(dt * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                         "sample": f"the whole {cam.width}x{cam.height} frame"}
+    n = min(soup_slice, wl.scene.n)
+    sc = wl.scene
+    raw = {"v": sc.v[:n].astype(np.float64), "a": np.log(sc.o[:n] / (1 - sc.o[:n] + 1e-7)),
+           "b": np.log(sc.sigma[:n]), "sh": sc.sh[:n].astype(np.float64)}
+    grads = {"v": rng.normal(0, 1e-3, raw["v"].shape), "o": rng.normal(0, 1e-3, n),
+             "sigma": rng.normal(0, 1e-3, n), "sh": rng.normal(0, 1e-3, raw["sh"].shape)}
+    state = {k: (np.zeros(np.shape(raw[k])), np.zeros(np.shape(raw[k]))) for k in raw}
+    t0 = time.perf_counter()
+    OT.optimizer_step(raw, grads, state, 1)
+    dt = time.perf_counter() - t0
+    out["optimizer"] = {"value": round(dt * 1e3 * sc.n / n, 1), "unit": "ms", "cores": 1,
+                        "kind": "oracle",
+                        "sample": f"{n} triangles in {dt:.2f} s, scaled to {sc.n}"}
+    u = rng.random(sc.n).astype(np.float32)
+    t0 = time.perf_counter()
+    sel = OD.select(sc.o, sc.sigma, OD.INV_SIGMA, 0.1 * sc.n, u)
+    OD.subdivide(sc.v, sc.o, sc.sigma, sc.sh, sel)
+    dt = time.perf_counter() - t0
+    out["densify"] = {"value": round(dt * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                      "sample": f"the whole {sc.n}-triangle soup, select + subdivide"}
+    return out
+
+
 def serve_bench(rates, duration, warmup, seed=5):
     """Forward-only serving of the resident 1M-triangle SH-3 soup: Poisson
     requests with resolutions from {640x360, 1280x720, 1920x1080} and
@@ -179,6 +238,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-other-view", action="store_true",
                     help="skip the second 3M-triangle view (1600x1040 for pose 0)")
+    ap.add_argument("--no-cpu-rows", action="store_true",
+                    help="skip timing the oracle beside the paths beyond the step")
     ap.add_argument("--no-train", action="store_true",
                     help="skip timing the synthetic training step")
     ap.add_argument("--no-densify", action="store_true",
@@ -492,6 +553,13 @@ def main():
         res["memory"]["fragment_note"] = (
             "F = composited fragments, the oracle's mean count on the sample pixels times W*H; "
             "a backward that stored them would keep >= 12 B each (index, alpha, T)")
+    if not args.no_cpu_baseline and not args.no_cpu_rows:
+        import dataclasses
+        log("[bench] timing the oracle beside the paths beyond the step")
+        res["cpu_rows"] = cpu_rows(wl, cam, {
+            "sigmoid": dataclasses.replace(cfg, window=synth.WINDOW_SIGMOID),
+            "lse": dataclasses.replace(cfg, window=synth.WINDOW_LSE)},
+            out.rgb.cpu().numpy().astype(np.float64))
     if not args.no_serve:
         rates = [int(r) for r in args.serve_rates.split(",")]
         res["serve"] = serve_bench(rates, args.serve_seconds, 0.5)
