@@ -135,7 +135,8 @@ typedef struct ts_bins {
     uint32_t* vals;     /* [capacity] triangle index of each instance, sorted */
     uint32_t* ranges;   /* [tiles][2] [start, end) of each tile in vals; (0,0) if empty */
     uint32_t* d_count;  /* [4] device counters: [0] instances M, [1] visible N_v,
-                           [2] overflow flag (M > capacity), [3] reserved */
+                           [2] overflow flag (M > capacity), [3] tiles holding more
+                           than 4096 instances */
     uint64_t capacity;  /* entries available in keys / vals */
     uint32_t* order;    /* [tiles] tiles by decreasing list length (the order in which
                            the rasterizers take them); may be NULL: natural order */
@@ -144,7 +145,14 @@ typedef struct ts_bins {
                            was composited; written by ts_render_forward, read by the
                            backward to skip the blocks where it contributed nothing
                            (2 bytes per instance, not per fragment); may be NULL */
+    uint32_t flags;     /* TS_BINS_SEGMENTED_SORT: depth-sort the tiles of more than 4096
+                           instances with a segmented radix sort spread over many
+                           workgroups (13 more launches) instead of one workgroup per
+                           tile; worth setting when d_count[3] of a similar view was
+                           non-zero (wide windows, dense or low-resolution views) */
 } ts_bins;
+
+#define TS_BINS_SEGMENTED_SORT 1u
 
 /* Bytes of one raster record (the layout is private to the library). */
 size_t ts_proj_record_bytes(void);

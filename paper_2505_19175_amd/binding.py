@@ -25,6 +25,7 @@ TS_CGRAD_STRIDE = 12
 TS_WINDOW_PAPER = 0
 TS_WINDOW_SIGMOID = 1
 TS_WINDOW_LSE = 2
+TS_BINS_SEGMENTED_SORT = 1
 TS_DENSIFY_OPACITY = 0
 TS_DENSIFY_INV_SIGMA = 1
 
@@ -66,7 +67,7 @@ class ts_bins(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p),
                 ("ranges", ctypes.c_void_p), ("d_count", ctypes.c_void_p),
                 ("capacity", ctypes.c_uint64), ("order", ctypes.c_void_p),
-                ("blocks", ctypes.c_void_p)]
+                ("blocks", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
 class ts_prune_stats(ctypes.Structure):

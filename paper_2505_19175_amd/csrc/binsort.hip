@@ -40,7 +40,8 @@ BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity, int64
     BinWorkspace w{};
     const int64_t nbN = nblocks(N > 0 ? N : 1);
     const int64_t nbC = nblocks(capacity > 0 ? (int64_t)capacity : 1);
-    w.hist_stride = nbC;
+    // the segmented sort's chunks: at most one partial chunk per tile more
+    w.hist_stride = nbC + (num_tiles > 0 ? num_tiles : 1);
     char* p = reinterpret_cast<char*>(base);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -59,6 +60,8 @@ BinWorkspace carve_bin_workspace(void* base, int64_t N, uint64_t capacity, int64
     w.tv[1] = take(c4);
     w.tfin = take(c4);
     w.torder = take(4 * (size_t)(num_tiles > 0 ? num_tiles : 1));
+    w.hl = take(4 * (size_t)(num_tiles > 0 ? num_tiles : 1));
+    w.cst = take(4 * (size_t)(num_tiles + 2));
     w.ctl = take(4 * 8);
     w.bytes = off;
     return w;
@@ -401,17 +404,22 @@ static_assert(kWaveMax < kLenBuckets - 1, "long tiles must lead the order");
 
 constexpr int kOrderThreads = 1024;
 
+constexpr int kHugeLen = 4 * kWaveMax;   // longest list one workgroup sorts in LDS
+
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(
     const uint32_t* __restrict__ ranges, int n_host, const uint32_t* __restrict__ d_n,
-    uint32_t* __restrict__ order, uint32_t* __restrict__ n_long)
+    uint32_t* __restrict__ order, uint32_t* __restrict__ n_long, uint32_t* __restrict__ n_huge)
 {
     __shared__ uint32_t h[kLenBuckets];
     __shared__ uint32_t s_w[kOrderThreads / 64];
-    __shared__ uint32_t s_long;
+    __shared__ uint32_t s_long, s_huge;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int n = d_n ? (int)min(*d_n, (uint32_t)n_host) : n_host;
     for (int b = tid; b < kLenBuckets; b += kOrderThreads) h[b] = 0u;
-    if (tid == 0) s_long = 0u;
+    if (tid == 0) {
+        s_long = 0u;
+        s_huge = 0u;
+    }
     __syncthreads();
     auto len_of = [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; };
     auto key = [&](int t) {
@@ -420,9 +428,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(
     for (int t = tid; t < n; t += kOrderThreads) {
         atomicAdd(&h[key(t)], 1u);
         if (len_of(t) > (uint32_t)kWaveMax) atomicAdd(&s_long, 1u);
+        if (len_of(t) > (uint32_t)kHugeLen) atomicAdd(&s_huge, 1u);
     }
     __syncthreads();
     if (n_long && tid == 0) n_long[0] = s_long;
+    if (n_huge && tid == 0) n_huge[0] = s_huge;
     // exclusive scan of the bucket counts, two consecutive buckets per thread
     static_assert(kLenBuckets == 2 * kOrderThreads, "two buckets per thread");
     const uint32_t a0 = h[2 * tid], a1 = h[2 * tid + 1], sum = a0 + a1;
@@ -443,11 +453,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(
 }
 
 void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
-                       uint32_t* order, hipStream_t stream, uint32_t* n_long)
+                       uint32_t* order, hipStream_t stream, uint32_t* n_long, uint32_t* n_huge)
 {
     if (order && num_tiles > 0)
         hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, stream, ranges,
-                           num_tiles, d_tiles, order, n_long);
+                           num_tiles, d_tiles, order, n_long, n_huge);
 }
 
 
@@ -485,7 +495,8 @@ __device__ __forceinline__ uint64_t tile_key(uint32_t t, uint32_t depth_bits)
 // s.cnt[r * 4 + w][d] is the number of keys of digit d in the (round, wave)
 // groups before (r, w), rank[r] the position of item r among the keys of its
 // digit in its own group, and the result the chunk's count of digit `tid`.
-__device__ uint32_t rank_chunk(const uint32_t (&key)[kItems], int n, int shift, SortSmem& s,
+template <class Smem>   // any shared struct with cnt[kItems * 4][kRadix]
+__device__ uint32_t rank_chunk(const uint32_t (&key)[kItems], int n, int shift, Smem& s,
                                uint32_t (&rank)[kItems])
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -834,7 +845,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
                                                    uint32_t* __restrict__ k0,
                                                    uint32_t* __restrict__ v0,
                                                    uint32_t* __restrict__ k1,
-                                                   uint32_t* __restrict__ v1)
+                                                   uint32_t* __restrict__ v1, int segmented)
 {
     __shared__ TileSortSmem sm;
     const uint32_t n = d_tiles ? min(*d_tiles, (uint32_t)num_tiles) : (uint32_t)num_tiles;
@@ -851,9 +862,9 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     const uint32_t s0 = ranges[2 * t];
     const int64_t L = (int64_t)ranges[2 * t + 1] - (int64_t)s0;
     const int w = threadIdx.x >> 6;
-    if (blockIdx.x < nl && L > 4 * kWaveMax) {   // the whole workgroup, in global memory
-        sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
-        return;
+    if (blockIdx.x < nl && L > kHugeLen) {   // the whole workgroup, in global memory
+        if (!segmented) sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
+        return;   // else the segmented sort below takes the tile
     }
     // one wave-level sort per wave: a whole tile, or a quarter of a long one
     const bool split = blockIdx.x < nl;          // the same for the whole workgroup
@@ -869,6 +880,207 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     if (split) {
         __syncthreads();   // every quarter sorted, and all reads of vals done
         merge_quarters((int)L, Q, s0, t, vals, keys, sm.wave);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4b. segmented depth sort of the tiles longer than kHugeLen entries: every
+// pass spreads each such tile over many workgroups (one per kChunk entries),
+// as the global passes of step 3 do -- per-chunk digit histograms, a scan per
+// tile over (digit, chunk), a stable scatter -- instead of one workgroup per
+// tile walking its chunks in turn.
+// ---------------------------------------------------------------------------
+
+// The huge tiles, listed from the first n_long entries of the order (they
+// lead it), and the prefix of their chunk counts: hl[k], cst[k] for k < nh,
+// cst[nh] = all chunks, cst[nh + 1] = nh.
+__global__ __launch_bounds__(kOrderThreads) void k_seg_plan(const uint32_t* __restrict__ ranges,
+                                                            const uint32_t* __restrict__ order,
+                                                            const uint32_t* __restrict__ n_long,
+                                                            int num_tiles,
+                                                            uint32_t* __restrict__ hl,
+                                                            uint32_t* __restrict__ cst)
+{
+    __shared__ uint32_t s_w[kOrderThreads / 64][2];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t nl = min(*n_long, (uint32_t)num_tiles);
+    uint32_t run_n = 0, run_c = 0;   // the same in every thread
+    for (uint32_t base = 0; base < nl; base += kOrderThreads) {
+        const uint32_t i = base + tid;
+        uint32_t t = 0, L = 0;
+        if (i < nl) {
+            t = order[i];
+            if (t < (uint32_t)num_tiles) L = ranges[2 * t + 1] - ranges[2 * t];
+        }
+        const uint32_t huge = L > (uint32_t)kHugeLen ? 1u : 0u;
+        const uint32_t ch = huge ? (L + kChunk - 1) / kChunk : 0u;
+        uint32_t a = huge, b = ch;   // inclusive wave scans
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ya = __shfl_up(a, d, 64), yb = __shfl_up(b, d, 64);
+            a += lane >= d ? ya : 0u;
+            b += lane >= d ? yb : 0u;
+        }
+        if (lane == 63) {
+            s_w[w][0] = a;
+            s_w[w][1] = b;
+        }
+        __syncthreads();
+        uint32_t pa = 0, pb = 0, ta = 0, tb = 0;
+        for (int k = 0; k < kOrderThreads / 64; ++k) {
+            pa += k < w ? s_w[k][0] : 0u;
+            pb += k < w ? s_w[k][1] : 0u;
+            ta += s_w[k][0];
+            tb += s_w[k][1];
+        }
+        if (huge) {
+            const uint32_t k = run_n + pa + a - 1;
+            hl[k] = t;
+            cst[k] = run_c + pb + b - ch;
+        }
+        run_n += ta;
+        run_c += tb;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        cst[run_n] = run_c;
+        cst[num_tiles + 1] = run_n;
+    }
+}
+
+// The chunk c of the segmented list: its huge tile k and its element range.
+struct SegChunk {
+    uint32_t t, s0, lo, n;
+    int k;
+};
+
+__device__ __forceinline__ bool seg_chunk(uint32_t c, const uint32_t* __restrict__ hl,
+                                          const uint32_t* __restrict__ cst, int num_tiles,
+                                          const uint32_t* __restrict__ ranges, SegChunk& q)
+{
+    const uint32_t nh = cst[num_tiles + 1];
+    if (nh == 0u || c >= cst[nh]) return false;
+    int lo = 0, hi = (int)nh - 1;   // the last k with cst[k] <= c
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cst[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    q.k = lo;
+    q.t = hl[lo];
+    q.s0 = ranges[2 * q.t];
+    const uint32_t L = ranges[2 * q.t + 1] - q.s0;
+    q.lo = (c - cst[lo]) * (uint32_t)kChunk;
+    q.n = min((uint32_t)kChunk, L - q.lo);
+    return true;
+}
+
+// Pass input: pass 0 reads the tile's entries from vals and their keys from
+// depth; later passes read the previous pass's (key, value) buffers.
+__device__ __forceinline__ void seg_load(const SegChunk& q, const uint32_t* __restrict__ kin,
+                                         const uint32_t* __restrict__ vin,
+                                         const float* __restrict__ depth,
+                                         uint32_t (&key)[kItems], uint32_t (&val)[kItems])
+{
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t j = (uint32_t)(r * kBlock + threadIdx.x);
+        key[r] = 0u;
+        val[r] = 0u;
+        if (j < q.n) {
+            const uint32_t pos = q.s0 + q.lo + j;
+            val[r] = vin[pos];
+            key[r] = kin ? kin[pos] : __float_as_uint(depth[val[r]]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_hist(const uint32_t* __restrict__ hl,
+                                                     const uint32_t* __restrict__ cst,
+                                                     int num_tiles,
+                                                     const uint32_t* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin,
+                                                     const float* __restrict__ depth, int shift,
+                                                     uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[kRadix];
+    SegChunk q;
+    if (!seg_chunk(blockIdx.x, hl, cst, num_tiles, ranges, q)) return;
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t key[kItems], val[kItems];
+    seg_load(q, kin, vin, depth, key, val);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+        if ((uint32_t)(r * kBlock + threadIdx.x) < q.n) atomicAdd(&h[(key[r] >> shift) & 0xffu], 1u);
+    __syncthreads();
+    hist[(int64_t)blockIdx.x * kRadix + threadIdx.x] = h[threadIdx.x];   // chunk-major
+}
+
+// One workgroup per huge tile, one thread per digit: the offsets of every
+// (digit, chunk) of the tile, in digit-major, chunk-minor order, written over
+// the histogram (chunk-major rows of 256 digits: each step of a thread's walk
+// over the chunks is one coalesced row access of the workgroup).
+__global__ __launch_bounds__(kBlock) void k_seg_scan(const uint32_t* __restrict__ hl,
+                                                     const uint32_t* __restrict__ cst,
+                                                     int num_tiles,
+                                                     const uint32_t* __restrict__ ranges,
+                                                     uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t tmp[4];
+    const uint32_t nh = cst[num_tiles + 1];
+    const uint32_t k = blockIdx.x;
+    if (k >= nh) return;
+    const uint32_t c0 = cst[k], c1 = cst[k + 1];
+    const uint32_t s0 = ranges[2 * hl[k]];
+    uint32_t* hd = hist + threadIdx.x;
+    uint32_t tot = 0;
+#pragma unroll 8
+    for (uint32_t c = c0; c < c1; ++c) tot += hd[(int64_t)c * kRadix];
+    uint32_t all;
+    uint32_t base = s0 + block_exclusive_scan(tot, all, tmp);
+#pragma unroll 8
+    for (uint32_t c = c0; c < c1; ++c) {
+        const uint32_t x = hd[(int64_t)c * kRadix];
+        hd[(int64_t)c * kRadix] = base;
+        base += x;
+    }
+}
+
+// What the segmented scatter keeps in LDS: the chunk's rank tables and digit
+// bases only (17 KB, so eight waves per SIMD fit).
+struct RankSmem {
+    uint16_t cnt[kItems * 4][kRadix];
+    uint32_t base[kRadix];
+};
+
+__global__ __launch_bounds__(kBlock) void k_seg_scatter(
+    const uint32_t* __restrict__ hl, const uint32_t* __restrict__ cst, int num_tiles,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ kin,
+    const uint32_t* __restrict__ vin, const float* __restrict__ depth, int shift,
+    const uint32_t* __restrict__ hist, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, uint64_t* __restrict__ keys)
+{
+    __shared__ RankSmem sm;
+    SegChunk q;
+    if (!seg_chunk(blockIdx.x, hl, cst, num_tiles, ranges, q)) return;
+    const int w = threadIdx.x >> 6;
+    uint32_t key[kItems], val[kItems], rank[kItems];
+    seg_load(q, kin, vin, depth, key, val);
+    rank_chunk(key, (int)q.n, shift, sm, rank);
+    // the chunk's first position for each digit, from the scanned histogram
+    sm.base[threadIdx.x] = hist[(int64_t)blockIdx.x * kRadix + threadIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if ((uint32_t)(r * kBlock + threadIdx.x) < q.n) {
+            const uint32_t d = (key[r] >> shift) & 0xffu;
+            const uint32_t pos = sm.base[d] + sm.cnt[r * 4 + w][d] + rank[r];
+            if (kout) kout[pos] = key[r];
+            vout[pos] = val[r];
+            if (keys) keys[pos] = tile_key(q.t, key[r]);
+        }
     }
 }
 
@@ -936,7 +1148,8 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
             // ranges are all empty here; keep the order valid for any raster
             // launched before the caller grows the list
             *overflow = true;
-            launch_tile_order(out.ranges, num_tiles, d_tiles, out.order, stream);
+            launch_tile_order(out.ranges, num_tiles, d_tiles, out.order, stream, nullptr,
+                              out.d_count + 3);
             return hipGetLastError();
         }
         m_max = h_count[0];
@@ -954,13 +1167,40 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
                            ws.tfin, d_sortn, out.ranges);
     uint32_t* order = out.order ? out.order : ws.torder;
     uint32_t* n_long = ws.ctl + 1;
-    launch_tile_order(out.ranges, num_tiles, d_tiles, order, stream, n_long);
+    launch_tile_order(out.ranges, num_tiles, d_tiles, order, stream, n_long, out.d_count + 3);
     // 4. depth order inside every tile
+    const bool seg = (out.flags & TS_BINS_SEGMENTED_SORT) != 0u;
     if (m_max > 0 && num_tiles > 0)
         hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)num_tiles), dim3(kBlock), 0, stream,
                            out.ranges, (const uint32_t*)order, (const uint32_t*)n_long, num_tiles,
                            d_tiles, depth, out.vals, out.keys, ws.tk[0], ws.tv[0], ws.tk[1],
-                           ws.tv[1]);
+                           ws.tv[1], seg ? 1 : 0);
+    if (seg && m_max > 0 && num_tiles > 0) {
+        // 4b. the huge tiles, spread over many workgroups: four stable passes
+        hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kOrderThreads), 0, stream, out.ranges,
+                           (const uint32_t*)order, (const uint32_t*)n_long, num_tiles, ws.hl,
+                           ws.cst);
+        const unsigned nc = (unsigned)(nblocks(m_max) + num_tiles);
+        const uint32_t* kin = nullptr;
+        const uint32_t* vin = out.vals;
+        for (int p = 0; p < 4; ++p) {
+            const bool last = p == 3;
+            uint32_t* kout = last ? nullptr : ws.tk[(p + 1) & 1];
+            uint32_t* vout = last ? out.vals : ws.tv[(p + 1) & 1];
+            hipLaunchKernelGGL(k_seg_hist, dim3(nc), dim3(kBlock), 0, stream,
+                               (const uint32_t*)ws.hl, (const uint32_t*)ws.cst, num_tiles,
+                               out.ranges, kin, vin, depth, 8 * p, ws.hist);
+            hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)num_tiles), dim3(kBlock), 0, stream,
+                               (const uint32_t*)ws.hl, (const uint32_t*)ws.cst, num_tiles,
+                               out.ranges, ws.hist);
+            hipLaunchKernelGGL(k_seg_scatter, dim3(nc), dim3(kBlock), 0, stream,
+                               (const uint32_t*)ws.hl, (const uint32_t*)ws.cst, num_tiles,
+                               out.ranges, kin, vin, depth, 8 * p, (const uint32_t*)ws.hist,
+                               kout, vout, last ? out.keys : nullptr);
+            kin = kout;
+            vin = vout;
+        }
+    }
     return hipGetLastError();
 }
 

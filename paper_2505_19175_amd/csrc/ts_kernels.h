@@ -58,7 +58,8 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream);
 // order[0..n) = tiles by decreasing list length, n = min(*d_tiles,
 // num_tiles) or num_tiles; nothing when order is null.
 void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
-                       uint32_t* order, hipStream_t stream, uint32_t* n_long = nullptr);
+                       uint32_t* order, hipStream_t stream, uint32_t* n_long = nullptr,
+                       uint32_t* n_huge = nullptr);
 
 // Workspace carve-up of the binning stage.
 struct BinWorkspace {
@@ -70,6 +71,8 @@ struct BinWorkspace {
     uint32_t* tv[2];    // [capacity] entry ids (ping-pong; per-tile sort scratch after)
     uint32_t* tfin;     // [capacity] sorted tile ids
     uint32_t* torder;   // [num_tiles] tile order when the caller keeps none
+    uint32_t* hl;       // [num_tiles] the tiles of the segmented sort
+    uint32_t* cst;      // [num_tiles + 2] their chunk prefix; [num_tiles + 1] = their count
     uint32_t* ctl;      // [8] device counters: [0] sort count min(M, capacity),
                         //     [1] tiles too long for the one-wave sort
     int64_t hist_stride;

@@ -51,6 +51,7 @@ class ViewState:
         self.order = torch.empty(max(self.num_tiles, 1), dtype=torch.int32, device=dev)
         self.d_count = torch.zeros(4, dtype=torch.int32, device=dev)
         self.want_keys = keys
+        self.segmented = False   # tiles of more than 4096 instances seen: segmented sort
         self._alloc_lists(capacity)
         self.proj = B.ts_proj(self.rec.data_ptr(), self.rect.data_ptr(), self.depth_key.data_ptr(),
                               self.ntiles.data_ptr(), self.g2d.data_ptr(),
@@ -70,7 +71,8 @@ class ViewState:
         self.bins = B.ts_bins(None if self.keys is None else self.keys.data_ptr(),
                               self.vals.data_ptr(), self.ranges.data_ptr(),
                               self.d_count.data_ptr(), self.capacity, self.order.data_ptr(),
-                              self.blocks.data_ptr())
+                              self.blocks.data_ptr(),
+                              B.TS_BINS_SEGMENTED_SORT if self.segmented else 0)
 
     def outputs(self) -> Outputs:
         dev, H, W = self.device, self.H, self.W
@@ -127,6 +129,11 @@ class Rasterizer:
             break
         if sync:
             st.M, st.N_v = int(st.count[0]), int(st.count[1])
+            # a view with tiles of more than 4096 instances: later calls on the
+            # same state sort those tiles with the segmented sort
+            if not st.segmented and int(st.d_count[3].item()) > 0:
+                st.segmented = True
+                st.bins.flags = B.TS_BINS_SEGMENTED_SORT
 
     def forward(self, st: ViewState, scene_t, cam, out: Optional[Outputs] = None,
                 sync: bool = True, stats: Optional["PruneStats"] = None) -> Outputs:

@@ -54,7 +54,7 @@ int main(void) {
   printf("ts_camera %zu\n", sizeof(ts_camera)); P(ts_camera, t); P(ts_camera, fx); P(ts_camera, width);
   printf("ts_config %zu\n", sizeof(ts_config)); P(ts_config, sh_degree); P(ts_config, bg); P(ts_config, window);
   printf("ts_proj %zu\n", sizeof(ts_proj)); P(ts_proj, g2d); P(ts_proj, cgrad);
-  printf("ts_bins %zu\n", sizeof(ts_bins)); P(ts_bins, d_count); P(ts_bins, capacity); P(ts_bins, order); P(ts_bins, blocks);
+  printf("ts_bins %zu\n", sizeof(ts_bins)); P(ts_bins, d_count); P(ts_bins, capacity); P(ts_bins, order); P(ts_bins, blocks); P(ts_bins, flags);
   printf("ts_prune_stats %zu\n", sizeof(ts_prune_stats)); P(ts_prune_stats, pixels);
   printf("ts_view %zu\n", sizeof(ts_view)); P(ts_view, tile_offset); P(ts_view, tiles_x); P(ts_view, pixel_offset);
   return 0;

@@ -216,6 +216,38 @@ def test_bins_one_deep_tile(n, mode):
     _check_bins(st, sc, cam, cfg)
 
 
+@pytest.mark.parametrize("n,mode", [(4097, "ulps"), (5000, "equal"), (20000, "spread"),
+                                    (20000, "ulps"), (45000, "wide")])
+def test_bins_segmented_sort(n, mode):
+    """Tiles of more than 4096 entries under the segmented sort (many
+    workgroups per tile): the sizing call reports the huge tile, the state
+    switches to the segmented sort, and the next call is bit-exact against
+    the oracle's stable sort."""
+    sc, cam = _one_tile_soup(62, n, mode)
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    assert st.segmented and int(st.d_count[3].item()) == 1
+    ras.forward(st, sct, cam, sync=True)
+    torch.cuda.synchronize()
+    _check_bins(st, sc, cam, cfg)
+
+
+def test_segmented_sort_many_tiles():
+    """A dense view where every tile holds thousands of entries: segmented
+    bins bit-exact, and the forward through them within the bar."""
+    sc, cam = random_soup(63, 40000, W=64, H=64, size=0.9, deg=0, sigma=(0.5, 2.0),
+                          o=(0.05, 0.6), zrange=(3.0, 4.0))
+    cfg = Config(sh_degree=0)
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    assert st.segmented and int(st.d_count[3].item()) >= 4
+    out = ras.forward(st, sct, cam, sync=True)
+    torch.cuda.synchronize()
+    _check_bins(st, sc, cam, cfg)
+    pix = synth.pixel_sample(64, cam.width, cam.height, 512)
+    ref = O.render(sc, cam, cfg, pix=pix)
+    G.assert_forward(G.to_np(out), ref, pix=pix, max_flag_frac=0.05)
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
