@@ -183,3 +183,64 @@ def test_fd_posed_camera_and_clamped_colour():
     assert (st["rgb"][st["vis"] == 1] == 0).any()     # some channels clamped
     for grp, seed in (("v", 13), ("sh", 14), ("o", 15)):
         _run_fd(sc, cam, cfg, grp, seed=seed, count=20)
+
+
+def test_opacity_gradient_homogeneity():
+    """alpha = o * I is linear in o below the clamp, so o dL/do equals
+    alpha dL/dalpha summed over the triangle's composited fragments
+    (clamped fragments contribute nothing).  With one pixel per backward each
+    triangle has at most one fragment; dL/dalpha comes from a front-to-back
+    composite written here, in which L is linear in each alpha, so the
+    derivative is L(alpha_i = 1) - L(alpha_i = 0) exactly."""
+    sc, cam = random_soup(27, 40, W=24, H=20, size=1.2, o=(0.3, 1.0))
+    sc.o[:8], sc.sigma[:8] = 1.0, 0.01     # opaque and flat: clamped inside
+    cfg = Config(sh_degree=0, T_min=0.0, bg=(0.2, 0.1, 0.3))
+    amin, amax = float(np.float32(cfg.alpha_min)), float(np.float32(cfg.alpha_max))
+    bg = np.array(cfg.bg, np.float32).astype(np.float64)
+    st = O.setup(sc, cam, cfg)
+    full = O.render(sc, cam, cfg)
+    rng = np.random.default_rng(16)
+    order = np.lexsort((np.arange(sc.n), st["key"]))
+    cand = np.argwhere(full["nfrag"] >= 3)
+    assert len(cand) > 20
+    # the pixels holding the opaque triangles' incentres, and a random sample
+    inc = [(int(st["s"][i, 1]), int(st["s"][i, 0])) for i in range(8) if st["vis"][i]]
+    inc = [(y, x) for y, x in inc if 0 <= x < cam.width and 0 <= y < cam.height]
+    checked = clamped = 0
+    for y, x in inc + [tuple(c) for c in cand[rng.choice(len(cand), 20, replace=False)]]:
+        p = (x + 0.5, y + 0.5)
+        alpha = np.zeros(sc.n)
+        for i in np.nonzero(st["vis"])[0]:
+            alpha[i] = float(sc.o[i]) * O.window(st["q"][i], p, float(sc.sigma[i]))[1]
+        assert not np.any(np.abs(alpha - amin) < 1e-9) and not np.any(np.abs(alpha - amax) < 1e-9)
+        frags = [i for i in order if st["vis"][i] and alpha[i] >= amin]
+        dC, dA, dD = rng.normal(size=3), rng.normal(), rng.normal()
+
+        def loss(a):
+            T, rgb, depth = 1.0, np.zeros(3), 0.0
+            for i in frags:
+                w = T * a[i]
+                rgb += w * st["rgb"][i]
+                depth += w * st["zc"][i]
+                T *= 1.0 - a[i]
+            return (dC * (rgb + T * bg)).sum() + dA * (1.0 - T) + dD * depth, rgb + T * bg, T, depth
+
+        alpha_c = np.minimum(alpha, amax)
+        L0, rgb, T, depth = loss(alpha_c)
+        pix = np.array([y * cam.width + x])
+        np.testing.assert_allclose(rgb, full["rgb"][:, y, x], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(1.0 - T, full["alpha"][y, x], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(depth, full["depth"][y, x], rtol=1e-12, atol=1e-14)
+        g = O.backward(sc, cam, cfg, dC.reshape(3, 1), np.array([dA]), np.array([dD]), pix=pix)
+        for i in range(sc.n):
+            if i in frags and alpha[i] < amax:
+                a1, a0 = alpha_c.copy(), alpha_c.copy()
+                a1[i], a0[i] = 1.0, 0.0
+                want = alpha[i] * (loss(a1)[0] - loss(a0)[0])
+                np.testing.assert_allclose(float(sc.o[i]) * g["o"][i], want,
+                                           rtol=1e-9, atol=1e-13)
+                checked += 1
+            else:
+                clamped += i in frags
+                assert g["o"][i] == 0.0
+    assert checked >= 40 and clamped >= 1

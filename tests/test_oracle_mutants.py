@@ -51,6 +51,7 @@ PINS = [
     ("fd sh", lambda: TG.test_fd_state_stable_pixels("sh", (1.0, 1.5))),
     ("fd posed", TG.test_fd_posed_camera_and_clamped_colour),
     ("fd clamp", TG.test_fd_clamped_and_terminated),
+    ("homogeneity", TG.test_opacity_gradient_homogeneity),
     ("tight box", lambda: TW.test_tight_box_brute_force(0)),
     ("over", lambda: TC.test_textbook_over_operator(3)),
     ("prune single", TP.test_single_triangle),
