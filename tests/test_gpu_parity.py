@@ -159,6 +159,26 @@ def test_large_workload_sampled(view):
     print("large", view, cam.width, cam.height, st.M, st.N_v, n_ok, n_flag, worst, s)
 
 
+@pytest.mark.parametrize("which", ["mid", "large"])
+def test_partition_of_unity_full_frame(which):
+    """With every colour 1 and a black background the image is sum_i w_i,
+    which must equal alpha = 1 - T_final (the weights and the final
+    transmittance telescope to 1) on every pixel of the full frame."""
+    wl = synth.workload_mid() if which == "mid" else synth.workload_large()
+    sc = wl.scene
+    sh = np.zeros_like(sc.sh)
+    sh[:, 0, :] = 0.5 * 2.0 * np.sqrt(np.pi)      # dc Y_0 = 1/2: colour 1
+    white = synth.Scene(sc.v, sc.o, sc.sigma, sh.astype(np.float32))
+    cfg = Config(sh_degree=wl.config.sh_degree)
+    ras, st, st_scene, out = G.gpu_forward(white, wl.cameras[0], cfg)
+    g = G.to_np(out)
+    np.testing.assert_array_equal(g["alpha"], 1.0 - g["T_final"].astype(np.float32))
+    err = np.abs(g["rgb"] - g["alpha"][None]).max()
+    print(which, "max |sum w - (1 - T_final)|", err, "covered", (g["alpha"] > 0).mean())
+    assert (g["alpha"] > 0).mean() > 0.2
+    assert err <= 1e-6
+
+
 def test_mid_bins_bit_exact():
     wl = synth.workload_mid()
     scene, cam, cfg = wl.scene, wl.cameras[0], wl.config
