@@ -398,7 +398,15 @@ def main():
             if r >= 0: ev[3 * r + 1].record(stream)
             B.ts_prune_count_views(ps.pixels, ps.views, N, sh_)
             if r >= 0: ev[3 * r + 2].record(stream)
+        # one more statistics pass, outside the timing: the per-triangle pixel
+        # counts sum to F, the number of composited fragments of the view
+        ps.pixels.zero_()
+        B.ts_render_forward_stats(st.proj, st.bins, ccam, ccfg, out.rgb, out.alpha, out.depth,
+                                  out.T_final, out.last, ps.c, sh_)
         torch.cuda.synchronize()
+        F = int(ps.pixels.sum(dtype=torch.int64).item())
+        res["fragments"] = F
+        res["memory"]["stored_fragment_bytes"] = 12 * F
         fwd_s = float(np.mean([ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(reps)]))
         cnt_s = float(np.mean([ev[3 * r + 1].elapsed_time(ev[3 * r + 2]) for r in range(reps)]))
         res["prune_stats"] = {
@@ -551,8 +559,10 @@ def main():
         res["memory"]["fragments_estimate"] = round(F_est)
         res["memory"]["stored_fragment_bytes_estimate"] = round(12 * F_est)
         res["memory"]["fragment_note"] = (
-            "F = composited fragments, the oracle's mean count on the sample pixels times W*H; "
-            "a backward that stored them would keep >= 12 B each (index, alpha, T)")
+            "fragments: F, composited fragments of the view, summed from the statistics "
+            "forward's per-triangle pixel counts; fragments_estimate: the oracle's mean count "
+            "on the sample pixels times W*H; a backward that stored them would keep >= 12 B "
+            "each (index, alpha, T)")
     if not args.no_cpu_baseline and not args.no_cpu_rows:
         import dataclasses
         log("[bench] timing the oracle beside the paths beyond the step")
