@@ -321,17 +321,25 @@ def main():
             step()
         torch.cuda.synchronize()
         assert int(stv.d_count[2].item()) == 0, "instance list overflow"
-        # timed region: exactly `steps` steps, per-stage events on the launch stream
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        # timed region: exactly `steps` steps, events only around them (events
+        # between the stages cost ~20 us a step, so they get a pass of their own)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
+        e0.record(stream)
+        for k in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        gpu_total_ms = float(e0.elapsed_time(e1))
+        # per-stage breakdown: the same steps again with events between the stages
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         for k in range(steps):
             step(evs[k])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
         per = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(5)]
                         for k in range(steps)])               # ms
-        gpu_total_ms = float(evs[0][0].elapsed_time(evs[-1][5]))
         return max(gpu_total_ms, wall * 1e3) / steps, per
 
     stages = ["project", "bin_sort", "raster_fwd", "raster_bwd", "project_bwd"]
@@ -446,39 +454,56 @@ def main():
         stt._alloc_lists(int(stt.M * 1.3) + 4096)
         gv_t, go_t, gs_t, gsh_t = ts.grads
 
-        def train_step(ev=None):
+        def train_step(ev=None, fused=True):
             if ev: ev[0].record(stream)
             ras.forward(stt, ts.scene_t(), cam, out=outt, sync=False)
             if ev: ev[1].record(stream)
             dCt = ts.image_loss(outt.rgb, tgt)
             if ev: ev[2].record(stream)
-            B.ts_render_backward(ts.v, ts.o, ts.sigma, ts.sh, N, stt.proj, stt.bins, stt.ccam,
-                                 ccfg, dCt, None, None, outt.T_final, outt.last, gv_t, go_t,
-                                 gs_t, gsh_t, sh_)
-            if ev: ev[3].record(stream)
             ts.t += 1
             ts.opt.step = ts.t
-            B.ts_optimizer_step(ts.v, ts.a, ts.b, ts.sh, ts.o, ts.sigma, ts.deg, N, gv_t, go_t,
-                                gs_t, gsh_t, ts.state, ts.opt, sh_)
+            if fused:
+                # Adam where each triangle's gradient is formed: no gradient arrays
+                B.ts_raster_backward(stt.proj, stt.bins, stt.ccam, ccfg, dCt, None, None,
+                                     outt.T_final, outt.last, sh_)
+                if ev: ev[3].record(stream)
+                B.ts_project_backward_adam(ts.v, ts.a, ts.b, ts.sh, ts.o, ts.sigma, N, stt.proj,
+                                           stt.ccam, ccfg, ts.state, ts.opt, sh_)
+            else:
+                B.ts_render_backward(ts.v, ts.o, ts.sigma, ts.sh, N, stt.proj, stt.bins,
+                                     stt.ccam, ccfg, dCt, None, None, outt.T_final, outt.last,
+                                     gv_t, go_t, gs_t, gsh_t, sh_)
+                if ev: ev[3].record(stream)
+                B.ts_optimizer_step(ts.v, ts.a, ts.b, ts.sh, ts.o, ts.sigma, ts.deg, N, gv_t,
+                                    go_t, gs_t, gsh_t, ts.state, ts.opt, sh_)
             if ev: ev[4].record(stream)
 
-        for _ in range(3):
-            train_step()
-        torch.cuda.synchronize()
-        loss0 = ts.loss_value()
+        def time_train(fused, reps=20):
+            for _ in range(3):
+                train_step(fused=fused)
+            torch.cuda.synchronize()
+            evt = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+            w0 = time.perf_counter()
+            for k in range(reps):
+                train_step(evt[k], fused)
+            torch.cuda.synchronize()
+            wall_t = (time.perf_counter() - w0) / reps * 1e3
+            assert int(stt.d_count[2].item()) == 0, "instance list overflow"
+            part = np.array([[evt[k][j].elapsed_time(evt[k][j + 1]) for j in range(4)]
+                             for k in range(reps)]).mean(0)
+            return max(float(evt[0][0].elapsed_time(evt[-1][4])) / reps, wall_t), part
+
         reps = 20
-        evt = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
-        w0 = time.perf_counter()
-        for k in range(reps):
-            train_step(evt[k])
-        torch.cuda.synchronize()
-        wall_t = (time.perf_counter() - w0) / reps * 1e3
-        assert int(stt.d_count[2].item()) == 0, "instance list overflow"
-        part = np.array([[evt[k][j].elapsed_time(evt[k][j + 1]) for j in range(4)]
-                         for k in range(reps)]).mean(0)
-        ms_t = max(float(evt[0][0].elapsed_time(evt[-1][4])) / reps, wall_t)
+        ms_sep, part_sep = time_train(False, reps)
+        loss0 = ts.loss_value()
+        ms_t, part = time_train(True, reps)
         K3 = 3 * K
         opt_bytes = N * (28.0 * (9 + K3) + 2 * 36.0)
+        # fused: per parameter read p, m, s and write them (24 B); the
+        # activated copies of o and sigma (16 B); rect and tile count (12 B);
+        # per visible triangle its 2D gradients read and re-zeroed and the
+        # colour Jacobian (176 B)
+        fused_bytes = N * (24.0 * (9 + K3 + 2) + 16 + 12) + stt.N_v * 176.0
         loss_bytes = 44.0 * 3 * W * H
         res["train_step"] = {
             "workload": f"tri3M_{W}x{H}: fit a copy of the soup with vertices moved by "
@@ -486,14 +511,25 @@ def main():
             "steps": reps, "ms_per_step": round(ms_t, 4),
             "Mpixel_per_s": round(W * H / (ms_t * 1e-3) / 1e6, 3),
             "stage_ms": {"forward": round(float(part[0]), 4), "image_loss": round(float(part[1]), 4),
-                         "backward": round(float(part[2]), 4),
-                         "optimizer": round(float(part[3]), 4)},
+                         "raster_backward": round(float(part[2]), 4),
+                         "backward_projection_adam": round(float(part[3]), 4)},
+            "backward_projection_adam_GBps_algorithmic":
+                round(fused_bytes / (part[3] * 1e-3) / 1e9, 1),
             "image_loss_GBps_algorithmic": round(loss_bytes / (part[1] * 1e-3) / 1e9, 1),
-            "optimizer_GBps_algorithmic": round(opt_bytes / (part[3] * 1e-3) / 1e9, 1),
+            "separate": {"ms_per_step": round(ms_sep, 4),
+                         "stage_ms": {"forward": round(float(part_sep[0]), 4),
+                                      "image_loss": round(float(part_sep[1]), 4),
+                                      "backward": round(float(part_sep[2]), 4),
+                                      "optimizer": round(float(part_sep[3]), 4)},
+                         "optimizer_GBps_algorithmic":
+                             round(opt_bytes / (part_sep[3] * 1e-3) / 1e9, 1)},
             "loss_first": round(loss0, 6), "loss_last": round(ts.loss_value(), 6),
-            "bytes_note": "optimizer: 28 B per parameter (read p, g, m, s; write p, m, s), 36 B "
-                          "for the opacity and sigma logits (their activated copies read and "
-                          "rewritten); image loss: 44 B per value"}
+            "bytes_note": "fused: the backward projection applies Adam where each triangle's "
+                          "gradient is formed (24 B per parameter, 16 B for the activated "
+                          "opacity and sigma, 12 B of tile data per triangle, 176 B per visible "
+                          "triangle); separate: the gradients are written, then the optimizer "
+                          "reads them (28 B per parameter, 36 B for each logit with its "
+                          "activated copy); image loss: 44 B per value"}
         del ts, stt, outt, tgt
     if not args.no_densify:
         # densification (Sec. 3.2) on the same soup: Bernoulli selection of

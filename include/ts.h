@@ -431,6 +431,28 @@ int ts_optimizer_step(float* v, float* a, float* b, float* sh, float* o, float* 
                       int sh_degree, int64_t N, float* gv, float* go, float* gsigma, float* gsh,
                       const ts_adam_state* state, const ts_optimizer* opt, hipStream_t stream);
 
+/* ts_project_backward_adam: ts_project_backward followed by ts_optimizer_step
+ * in one pass over the triangles (Sec. 3.3: the training step's backward and
+ * Adam update).  Triangles share no parameters, so a triangle's gradient is
+ * complete once its own 2D gradients are chained back; the optimizer step
+ * runs on it there, and no gradient array is written or read.  For callers
+ * that train and need no gradients.
+ *   v [N][3][3], a, b [N], sh [N][(deg+1)^2][3]: raw parameters (device), the
+ *                ones the view was rendered with; updated in place
+ *   o, sigma [N]: their activated copies (read, then rewritten)
+ *   proj, cam, cfg: as for ts_project_backward (after ts_raster_backward);
+ *                the SH degree is cfg->sh_degree; proj->g2d is consumed
+ *                (re-zeroed)
+ *   state, opt: as for ts_optimizer_step
+ * The result is that of the two calls: both run the same FP32 steps, so it
+ * differs only where the compiler contracted an expression differently.
+ * TS_EINVAL for the arguments either call rejects.
+ */
+int ts_project_backward_adam(float* v, float* a, float* b, float* sh, float* o, float* sigma,
+                             int64_t N, const ts_proj* proj, const ts_camera* cam,
+                             const ts_config* cfg, const ts_adam_state* state,
+                             const ts_optimizer* opt, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

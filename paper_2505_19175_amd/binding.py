@@ -35,7 +35,8 @@ EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes"
            "ts_project_backward", "ts_batch_layout", "ts_batch_workspace_bytes",
            "ts_render_forward_batched", "ts_densify_workspace_bytes", "ts_densify_select",
            "ts_densify_subdivide", "ts_image_loss_workspace_bytes", "ts_image_loss",
-           "ts_optimizer_step", "ts_error_string", "ts_last_error")
+           "ts_optimizer_step", "ts_project_backward_adam", "ts_error_string",
+           "ts_last_error")
 
 
 class TSError(RuntimeError):
@@ -153,6 +154,10 @@ def load():
     L.ts_optimizer_step.argtypes = [P, P, P, P, P, P, ctypes.c_int, I64, P, P, P, P,
                                     ctypes.POINTER(ts_adam_state), ctypes.POINTER(ts_optimizer),
                                     P]
+    L.ts_project_backward_adam.restype = ctypes.c_int
+    L.ts_project_backward_adam.argtypes = [P, P, P, P, P, P, I64, PP, PC, PG,
+                                           ctypes.POINTER(ts_adam_state),
+                                           ctypes.POINTER(ts_optimizer), P]
     L.ts_error_string.restype = ctypes.c_char_p
     L.ts_error_string.argtypes = [ctypes.c_int]
     L.ts_last_error.restype = ctypes.c_char_p
@@ -251,6 +256,15 @@ def ts_project_backward(v, sh, N: int, proj: ts_proj, cam: ts_camera, cfg: ts_co
     _check(load().ts_project_backward(_ptr(v), _ptr(sh), N, ctypes.byref(proj), ctypes.byref(cam),
                                       ctypes.byref(cfg), _ptr(gv), _ptr(go), _ptr(gsigma),
                                       _ptr(gsh), stream), "ts_project_backward")
+
+
+def ts_project_backward_adam(v, a, b, sh, o, sigma, N: int, proj: ts_proj, cam: ts_camera,
+                             cfg: ts_config, state: ts_adam_state, opt: ts_optimizer,
+                             stream: int = 0):
+    _check(load().ts_project_backward_adam(_ptr(v), _ptr(a), _ptr(b), _ptr(sh), _ptr(o),
+                                           _ptr(sigma), N, ctypes.byref(proj), ctypes.byref(cam),
+                                           ctypes.byref(cfg), ctypes.byref(state),
+                                           ctypes.byref(opt), stream), "ts_project_backward_adam")
 
 
 def ts_batch_layout(views, n: int):

@@ -403,6 +403,35 @@ int ts_optimizer_step(float* v, float* a, float* b, float* sh, float* o, float* 
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_optimizer_step");
 }
 
+int ts_project_backward_adam(float* v, float* a, float* b, float* sh, float* o, float* sigma,
+                             int64_t N, const ts_proj* proj, const ts_camera* cam,
+                             const ts_config* cfg, const ts_adam_state* st,
+                             const ts_optimizer* opt, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_project_backward_adam: N out of range");
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_project_backward_adam: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_project_backward_adam: bad config");
+    if (!opt || opt->step < 1 || !st)
+        return fail(TS_EINVAL, "ts_project_backward_adam: bad step or null settings");
+    if (N == 0) return TS_OK;
+    if (!proj_ok(proj) || !proj->cgrad || !v || !a || !b || !sh || !o || !sigma || !st->m_v ||
+        !st->s_v || !st->m_a || !st->s_a || !st->m_b || !st->s_b || !st->m_sh || !st->s_sh)
+        return fail(TS_EINVAL, "ts_project_backward_adam: null pointer");
+    const float bc1 = (float)(1.0 - pow((double)opt->beta1, opt->step));
+    const float bc2 = (float)(1.0 - pow((double)opt->beta2, opt->step));
+    float* const state[8] = {st->m_v, st->s_v, st->m_a, st->s_a, st->m_b, st->s_b, st->m_sh,
+                             st->s_sh};
+    const float lr[5] = {opt->lr_v, opt->lr_opacity, opt->lr_sigma, opt->lr_sh_dc,
+                         opt->lr_sh_rest};
+    ts::launch_backproject_adam(v, a, b, sh, o, sigma, proj->cgrad, N, to_cam(cam), to_cfg(cfg),
+                                proj->rect, proj->ntiles, proj->g2d, state, lr,
+                                opt->beta_opacity, opt->beta_size, opt->beta1, opt->beta2, bc1,
+                                bc2, opt->eps, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project_backward_adam");
+}
+
 size_t ts_densify_workspace_bytes(int64_t N) { return ts::densify_workspace_bytes(N < 0 ? 0 : N); }
 
 int ts_densify_select(const float* o, const float* sigma, int64_t N, int mode, double k_expected,

@@ -9,6 +9,7 @@
 // HBM; the optimizer kernels stream every parameter array once (HBM).
 #include <math.h>
 
+#include "adam.h"
 #include "ts_device.h"
 #include "ts_kernels.h"
 
@@ -252,26 +253,13 @@ void launch_image_loss(const float* rgb, const float* target, int W, int H, floa
 }
 
 // ---------------------------------------------------------------------------
-// Adam with the regularizers and the activation chain folded in.
-//
-// Vertices, one triangle per thread: g = gv + beta_s d/dv mean 2/|c|,
-// c = (v1 - v0) x (v2 - v0), then the update of its nine coordinates.
+// Adam with the regularizers and the activation chain folded in (the
+// arithmetic is in adam.h, shared with the backward projection's fused step).
 // ---------------------------------------------------------------------------
-struct AdamK {
-    float b1, b2, bc1, bc2, eps;
-};
 
-__device__ __forceinline__ float adam_update(float p, float g, float& m, float& s, float lr,
-                                             const AdamK& k)
-{
-    m = fmaf(k.b1, m, (1.f - k.b1) * g);
-    s = fmaf(k.b2, s, (1.f - k.b2) * g * g);
-    return p - lr * (m / k.bc1) / (sqrtf(s / k.bc2) + k.eps);
-}
-
-// The block's 256 vertex and gradient rows are staged through LDS so every
-// global access is coalesced; each thread adds its triangle's size-loss
-// gradient in LDS, then the update runs element-wise.
+// Vertices: the block's 256 vertex and gradient rows are staged through LDS
+// so every global access is coalesced; each thread adds its triangle's
+// size-loss gradient in LDS, then the update runs element-wise.
 __global__ __launch_bounds__(256) void k_adam_vertices(float* __restrict__ v,
                                                        const float* __restrict__ gv,
                                                        float* __restrict__ m, float* __restrict__ s,
@@ -288,31 +276,7 @@ __global__ __launch_bounds__(256) void k_adam_vertices(float* __restrict__ v,
     }
     __syncthreads();
     const int t = threadIdx.x;
-    if (t < nt && beta_s != 0.f) {
-        const float* p = sv + 9 * t;
-        float* g = sg + 9 * t;
-        const float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
-        const float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
-        const float c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                            e1[0] * e2[1] - e1[1] * e2[0]};
-        const float n2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-        if (n2 > 0.f) {
-            const float inv = rsqrtf(n2);
-            const float kk = -2.f * beta_s / (float)N * inv * inv * inv;   // dL/dc = kk c
-            const float gc[3] = {kk * c[0], kk * c[1], kk * c[2]};
-            // c = e1 x e2: dL/de1 = e2 x gc, dL/de2 = gc x e1
-            const float g1[3] = {e2[1] * gc[2] - e2[2] * gc[1], e2[2] * gc[0] - e2[0] * gc[2],
-                                 e2[0] * gc[1] - e2[1] * gc[0]};
-            const float g2[3] = {gc[1] * e1[2] - gc[2] * e1[1], gc[2] * e1[0] - gc[0] * e1[2],
-                                 gc[0] * e1[1] - gc[1] * e1[0]};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                g[a] -= g1[a] + g2[a];
-                g[3 + a] += g1[a];
-                g[6 + a] += g2[a];
-            }
-        }
-    }
+    if (t < nt && beta_s != 0.f) size_loss_grad(sv + 9 * t, sg + 9 * t, beta_s, N);
     __syncthreads();
     for (int f = threadIdx.x; f < n; f += 256) {
         float mi = m[off + f], si = s[off + f];
@@ -322,12 +286,9 @@ __global__ __launch_bounds__(256) void k_adam_vertices(float* __restrict__ v,
     }
 }
 
-// Flat Adam; element e uses lr_a when e % row < first, else lr_b.
-//   act 0: g as given
-//   act 1: opacity logit: g = (g + add) y (1 - y), y = out[e] = sigmoid of the
-//          old value; out[e] becomes sigmoid of the new one
-//   act 2: log sigma: g = g y, y = out[e] = exp of the old value; out[e]
-//          becomes exp of the new one
+// Flat Adam; element e uses lr_a when e % row < first, else lr_b; act as in
+// act_grad (0: g as given); with act 1 or 2, out[e] holds the activated old
+// value and becomes the activated new one.
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ s,
                                               int64_t n, int row, int first, float lr_a, float lr_b,
@@ -336,21 +297,14 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
-    float gi = g[e];
-    if (act == 1) {
-        const float y = out[e];
-        gi = (gi + add) * y * (1.f - y);
-    } else if (act == 2) {
-        gi *= out[e];
-    }
+    const float gi = act != 0 ? act_grad(g[e], act, add, out[e]) : g[e];
     float mi = m[e], si = s[e];
     const float lr = (int)(e % row) < first ? lr_a : lr_b;
     const float pi = adam_update(p[e], gi, mi, si, lr, k);
     m[e] = mi;
     s[e] = si;
     p[e] = pi;
-    if (act == 1) out[e] = 1.f / (1.f + expf(-pi));
-    else if (act == 2) out[e] = expf(pi);
+    if (act != 0) out[e] = act_value(pi, act);
 }
 
 void launch_optimizer(float* v, float* a, float* b, float* sh, float* o, float* sigma, int nsh,

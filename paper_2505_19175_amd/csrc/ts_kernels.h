@@ -116,6 +116,16 @@ void launch_optimizer(float* v, float* a, float* b, float* sh, float* o, float* 
                       float beta_s, float b1, float b2, float bc1, float bc2, float eps,
                       hipStream_t stream);
 
+// The backward projection and the optimizer step in one pass (Adam where
+// each triangle's gradient is formed); st, lr and the constants as for
+// launch_optimizer.
+void launch_backproject_adam(float* v, float* a, float* b, float* sh, float* o, float* sigma,
+                             const float* cgrad, int64_t N, const Cam& cam, const Cfg& cfg,
+                             const int16_t* rect, const uint32_t* ntiles, float* g2d,
+                             float* const* st, const float* lr, float beta_o, float beta_s,
+                             float b1, float b2, float bc1, float bc2, float eps,
+                             hipStream_t stream);
+
 // views[i] += pixels[i] > 1; pixels[i] = 0.
 void launch_prune_views(uint32_t* pixels, uint32_t* views, int64_t N, hipStream_t stream);
 

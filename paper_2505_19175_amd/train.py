@@ -72,19 +72,27 @@ class TrainState:
         return self.dC
 
     def step(self, ras: Rasterizer, st: ViewState, cam, target, sync: bool = False,
-             stats=None) -> Outputs:
+             stats=None, fused: bool = True) -> Outputs:
         """forward -> image loss -> backward -> regularizers + Adam.  With
         stats (render.PruneStats) the forward also keeps the pruning
-        statistics of the view."""
+        statistics of the view.  fused: the backward projection applies Adam
+        where each triangle's gradient is formed (no gradient arrays); else
+        the gradients are written to self.grads and the optimizer reads them."""
         stream = torch.cuda.current_stream().cuda_stream
         out = ras.forward(st, self.scene_t(), cam, sync=sync, stats=stats)
         dC = self.image_loss(out.rgb, target)
+        self.t += 1
+        self.opt.step = self.t
+        if fused:
+            B.ts_raster_backward(st.proj, st.bins, st.ccam, ras.ccfg, dC, None, None, out.T_final,
+                                 out.last, stream)
+            B.ts_project_backward_adam(self.v, self.a, self.b, self.sh, self.o, self.sigma, self.N,
+                                       st.proj, st.ccam, ras.ccfg, self.state, self.opt, stream)
+            return out
         gv, go, gs, gsh = self.grads
         B.ts_render_backward(self.v, self.o, self.sigma, self.sh, self.N, st.proj, st.bins,
                              st.ccam, ras.ccfg, dC, None, None, out.T_final, out.last, gv, go, gs,
                              gsh, stream)
-        self.t += 1
-        self.opt.step = self.t
         B.ts_optimizer_step(self.v, self.a, self.b, self.sh, self.o, self.sigma, self.deg, self.N,
                             gv, go, gs, gsh, self.state, self.opt, stream)
         return out

@@ -118,3 +118,17 @@ def test_argument_checks_need_no_gpu():
     with pytest.raises(B.TSError) as e:
         B.ts_optimizer_step(1, 1, 1, 1, 1, 1, 4, 10, 1, 1, 1, 1, st, B.ts_optimizer(step=1))
     assert e.value.code == B.TS_EINVAL
+    # the fused backward projection + optimizer: bad step, bad config, null
+    # parameter, null projection state
+    from paper_2505_19175_amd import synth
+    cam = B.make_camera(synth.identity_camera(32, 32))
+    cfg = B.make_config(synth.Config(sh_degree=1))
+    proj = B.ts_proj(16, 16, 16, 16, 16)
+    for kw, args in ((dict(step=0), (1, 1, 1, 1, 1, 1, 10, proj, cam, cfg)),
+                     (dict(step=1), (1, 1, 1, 1, 1, 1, 10, proj, cam,
+                                     B.make_config(synth.Config(sh_degree=7)))),
+                     (dict(step=1), (1, None, 1, 1, 1, 1, 10, proj, cam, cfg)),
+                     (dict(step=1), (1, 1, 1, 1, 1, 1, 10, B.ts_proj(), cam, cfg))):
+        with pytest.raises(B.TSError) as e:
+            B.ts_project_backward_adam(*args, st, B.ts_optimizer(**kw))
+        assert e.value.code == B.TS_EINVAL

@@ -157,3 +157,56 @@ def test_fit_lowers_the_loss():
     views = ps.views.cpu().numpy()
     assert views.max() == 2 and (views == 2).sum() > 100
     assert 0.0 < float(ps.max_weight.max()) <= 1.0
+
+
+@pytest.mark.parametrize("deg,window", [(1, synth.WINDOW_PAPER), (3, synth.WINDOW_PAPER),
+                                        (3, synth.WINDOW_LSE)])
+def test_fused_backward_adam_matches_separate_calls(deg, window):
+    """Three training steps of two copies of the parameters: one with the
+    backward projection applying Adam where each triangle's gradient is
+    formed, one with the gradients written out and the optimizer reading
+    them.  Both take the same 2D gradients each step (one raster backward,
+    whose FP32 atomics add in any order, saved and restored between them),
+    so the same FP32 steps must give the same parameters, activated copies
+    and moments.  Triangles behind the camera take the regularizer-only
+    update on both paths."""
+    sc, cam = _soup64(62, 3000, W=160, H=120, size=0.8, deg=deg, o=(0.3, 0.9), dtype=np.float32)
+    sc.v[:100, :, 2] = -1.0                      # behind the camera: culled
+    cfg = dataclasses.replace(synth.Config(sh_degree=deg), window=window)
+    ras = Rasterizer(cfg, device=DEV)
+    tgt_scene = dataclasses.replace(sc, v=(sc.v + np.random.default_rng(2).normal(
+        0, 0.03, sc.v.shape)).astype(np.float32))
+    st = ViewState(sc.n, cam.width, cam.height, 1 << 18, device=DEV)
+    target = ras.forward(st, scene_to_device(tgt_scene, DEV), cam).rgb.clone()
+    fu, sep = (TrainState(sc, device=DEV, beta_size=1e-3) for _ in range(2))
+    N = sc.n
+    for t in range(1, 4):
+        out = ras.forward(st, fu.scene_t(), cam, sync=True)
+        dC = fu.image_loss(out.rgb, target)
+        B.ts_raster_backward(st.proj, st.bins, st.ccam, ras.ccfg, dC, None, None, out.T_final,
+                             out.last)
+        g2d = st.g2d.clone()
+        fu.opt.step = sep.opt.step = t
+        B.ts_project_backward_adam(fu.v, fu.a, fu.b, fu.sh, fu.o, fu.sigma, N, st.proj, st.ccam,
+                                   ras.ccfg, fu.state, fu.opt)
+        assert torch.count_nonzero(st.g2d).item() == 0       # consumed
+        st.g2d.copy_(g2d)
+        gv, go, gs, gsh = sep.grads
+        B.ts_project_backward(sep.v, sep.sh, N, st.proj, st.ccam, ras.ccfg, gv, go, gs, gsh)
+        B.ts_optimizer_step(sep.v, sep.a, sep.b, sep.sh, sep.o, sep.sigma, deg, N, gv, go, gs,
+                            gsh, sep.state, sep.opt)
+        torch.cuda.synchronize()
+        same = total = 0
+        for name in ("v", "a", "b", "sh", "o", "sigma"):
+            x, y = (getattr(ts, name).cpu().numpy() for ts in (fu, sep))
+            np.testing.assert_allclose(x, y, rtol=1e-6, atol=1e-9, err_msg=f"{name} t={t}")
+            same += int((x == y).sum())
+            total += x.size
+        for k, (ma, mb) in enumerate(zip(fu.moments, sep.moments)):
+            x, y = ma.cpu().numpy(), mb.cpu().numpy()
+            np.testing.assert_allclose(x, y, rtol=1e-5, atol=1e-15 if k % 2 == 0 else 1e-25,
+                                       err_msg=f"moment {k} t={t}")
+            same += int((x == y).sum())
+            total += x.size
+        print(f"step {t}: {same}/{total} values bit-identical")
+    assert np.isfinite(fu.loss_value())
