@@ -40,7 +40,7 @@ TRAFFIC = {
     "project_bwd": {"files": ["paper_2505_19175_amd/csrc/backproject.hip",
                               "paper_2505_19175_amd/csrc/geometry.h",
                               "paper_2505_19175_amd/csrc/ts_device.h"],
-                    "src": "7f8509e7dfcc970303f83dc503d74aae5d1bf14384045ec9615103f1bbb4b65f",
+                    "src": "515adcd01565f54effe06e7915fd57d6cc3300f6f63e87284033302fb871932e",
                     "fetch_kib": 1.6148e5, "write_kib": 7.8067e5,
                     "fetch_scale": 2.0, "write_scale": 1.0},
     "project": {"files": ["paper_2505_19175_amd/csrc/project.hip",

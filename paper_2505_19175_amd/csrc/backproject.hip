@@ -1,5 +1,7 @@
 // backproject.hip -- the chain from the per-triangle 2D gradients to the
-// triangle parameters (backward).  One thread per triangle; geometry in FP64.
+// triangle parameters (backward), and the same chain with the training
+// step's Adam update applied in place.  One thread per triangle; geometry in
+// FP64.
 #include "adam.h"
 #include "geometry.h"
 #include "ts_kernels.h"
