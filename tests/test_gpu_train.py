@@ -159,9 +159,16 @@ def test_fit_lowers_the_loss():
     assert 0.0 < float(ps.max_weight.max()) <= 1.0
 
 
-@pytest.mark.parametrize("deg,window", [(1, synth.WINDOW_PAPER), (3, synth.WINDOW_PAPER),
-                                        (3, synth.WINDOW_LSE)])
-def test_fused_backward_adam_matches_separate_calls(deg, window):
+# (n, degree, window): 3000 triangles end in a block of 184, so the vertex and
+# (degree 1, 3) SH spans move as 16-byte vectors; 3001 and 2999 end in blocks
+# of 185 and 183 (9 * nt not a multiple of 4) and degrees 0 and 2 have 3 and
+# 27 SH floats a row: the element-wise paths
+@pytest.mark.parametrize("n,deg,window", [(3000, 1, synth.WINDOW_PAPER),
+                                          (3000, 3, synth.WINDOW_PAPER),
+                                          (3000, 3, synth.WINDOW_LSE),
+                                          (3001, 0, synth.WINDOW_PAPER),
+                                          (2999, 2, synth.WINDOW_SIGMOID)])
+def test_fused_backward_adam_matches_separate_calls(n, deg, window):
     """Three training steps of two copies of the parameters: one with the
     backward projection applying Adam where each triangle's gradient is
     formed, one with the gradients written out and the optimizer reading
@@ -170,7 +177,7 @@ def test_fused_backward_adam_matches_separate_calls(deg, window):
     so the same FP32 steps must give the same parameters, activated copies
     and moments.  Triangles behind the camera take the regularizer-only
     update on both paths."""
-    sc, cam = _soup64(62, 3000, W=160, H=120, size=0.8, deg=deg, o=(0.3, 0.9), dtype=np.float32)
+    sc, cam = _soup64(62, n, W=160, H=120, size=0.8, deg=deg, o=(0.3, 0.9), dtype=np.float32)
     sc.v[:100, :, 2] = -1.0                      # behind the camera: culled
     cfg = dataclasses.replace(synth.Config(sh_degree=deg), window=window)
     ras = Rasterizer(cfg, device=DEV)
