@@ -8,6 +8,10 @@ BatchedExecutor  -- `slots` independent buffer sets, each with its own HIP
 PlainExecutor    -- the baseline: one view per launch on one stream, the
                     staged pipeline ts_project -> ts_bin_sort (host read of
                     the instance count) -> ts_render_forward, no graph.
+
+With d2h set, either executor also copies each batch's colour images into
+pinned host memory (allocated up front) after the render, and a batch is
+complete once that copy is: latency then includes the transfer to the host.
 """
 from __future__ import annotations
 
@@ -30,7 +34,7 @@ class _Slot:
 class BatchedExecutor:
     def __init__(self, scene_t, cfg, clock, max_views: int = 8, max_tiles: int = 8 * 8160,
                  max_pixels: int = 8 * 1920 * 1080, capacity: int = 4 << 20, slots: int = 2,
-                 use_graph: bool = True, device="cuda"):
+                 use_graph: bool = True, device="cuda", d2h: bool = False):
         self.scene_t = scene_t
         self.N = int(scene_t[0].shape[0])
         self.cfg = B.make_config(cfg)
@@ -38,6 +42,7 @@ class BatchedExecutor:
         self.max_views, self.max_tiles, self.max_pixels = max_views, max_tiles, max_pixels
         self.capacity, self.slots = capacity, slots
         self.use_graph = use_graph
+        self.d2h = d2h
         dev = torch.device(device)
         n = self.N * max_views
         self.ws_bytes = B.ts_batch_workspace_bytes(self.N, max_views, capacity, max_tiles)
@@ -60,6 +65,8 @@ class BatchedExecutor:
             s.desc_dev = torch.zeros(desc_bytes, dtype=torch.uint8, device=dev)
             s.desc_host = torch.zeros(desc_bytes, dtype=torch.uint8).pin_memory()
             s.count_host = torch.zeros(4, dtype=torch.int32).pin_memory()
+            s.rgb_host = (torch.empty(3 * max_pixels, dtype=torch.float32, pin_memory=True)
+                          if d2h else None)
             s.views = (B.ts_view * max_views)()
             s.proj = B.ts_proj(s.rec.data_ptr(), s.rect.data_ptr(), s.depth_key.data_ptr(),
                                s.ntiles.data_ptr(), None)
@@ -120,6 +127,8 @@ class BatchedExecutor:
                 s.graph.replay()
             else:
                 self._launch(s, s.stream.cuda_stream)
+            if self.d2h:   # the views' colour images are contiguous from offset 0
+                s.rgb_host[: 3 * pixels].copy_(s.rgb[: 3 * pixels], non_blocking=True)
             s.event.record(s.stream)
             s.count_host.copy_(s.d_count, non_blocking=True)
 
@@ -149,7 +158,8 @@ class BatchedExecutor:
 class PlainExecutor:
     """One view per launch, FIFO, one stream, no graph."""
 
-    def __init__(self, scene_t, cfg, clock, capacity: int = 4 << 20, device="cuda"):
+    def __init__(self, scene_t, cfg, clock, capacity: int = 4 << 20, device="cuda",
+                 d2h: bool = False):
         from ..render import Rasterizer
         self.scene_t = scene_t
         self.N = int(scene_t[0].shape[0])
@@ -161,18 +171,24 @@ class PlainExecutor:
         self.outs = {}
         self.event = torch.cuda.Event()
         self.batch = None
+        self.d2h = d2h
+        self.hosts = {}
 
     def _state(self, W, H):
         key = (W, H)
         if key not in self.states:
             self.states[key] = ViewState(self.N, W, H, self.capacity)
             self.outs[key] = self.states[key].outputs()
+            if self.d2h:
+                self.hosts[key] = torch.empty((3, H, W), dtype=torch.float32, pin_memory=True)
         return self.states[key], self.outs[key]
 
     def submit(self, slot: int, batch: List[Request]) -> None:
         (r,) = batch
         st, out = self._state(r.camera.width, r.camera.height)
         self.ras.forward(st, self.scene_t, r.camera, out=out, sync=True)
+        if self.d2h:
+            self.hosts[(r.camera.width, r.camera.height)].copy_(out.rgb, non_blocking=True)
         self.event.record()
         self.batch = batch
         self.last = (st, out)

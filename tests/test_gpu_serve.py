@@ -111,3 +111,30 @@ def test_short_load_run_completes(soup):
                   seed=4)
     assert s2["n"] == s["n"] and np.isfinite(s2["p99_ms"])
     print("batched", s, "plain", s2)
+
+
+def test_host_copy_holds_the_images(soup):
+    """With the host copy on, a completed batch's pinned host buffer holds
+    every view's colour image, bit for bit, and the plain executor's host
+    image equals its device image."""
+    sc, cfg, st = soup
+    cams = _cams(5, [(640, 360), (320, 200), (1280, 720)])
+    ex = BatchedExecutor(st, cfg, time.perf_counter, max_views=3, max_tiles=3 * 3600,
+                         max_pixels=3 * 1280 * 720, capacity=1 << 21, slots=2, d2h=True)
+    for k, mix in enumerate([[0, 1, 2], [2, 0], [1]]):
+        slot = k % 2
+        batch = [Request(i, cams[i], 0.0) for i in mix]
+        ex.submit(slot, batch)
+        _wait(ex, slot)
+        views, _, _ = ex.layout(batch)
+        host = ex._slots[slot].rgb_host.numpy()
+        for j, (i, (rgb, _, _)) in enumerate(zip(mix, ex.outputs(slot, batch))):
+            po, W, H = int(views[j].pixel_offset), cams[i].width, cams[i].height
+            np.testing.assert_array_equal(host[3 * po: 3 * po + 3 * W * H].reshape(3, H, W),
+                                          rgb.cpu().numpy())
+    px = PlainExecutor(st, cfg, time.perf_counter, d2h=True)
+    cam = cams[1]
+    px.submit(0, [Request(0, cam, 0.0)])
+    _wait(px, 0)
+    np.testing.assert_array_equal(px.hosts[(cam.width, cam.height)].numpy(),
+                                  px.outs[(cam.width, cam.height)].rgb.cpu().numpy())
