@@ -195,6 +195,28 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
                 const ts_bins* out, uint32_t* h_count, hipStream_t stream);
 
 /*
+ * ts_bin_sort without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as ts_bin_sort; the workspace is a fixed device array of
+ * TS_NOALLOC_SCRATCH_BYTES inside the library (one copy per GPU, held until
+ * the process ends).  The call allocates nothing: its first call on a
+ * device, with that device current, resolves the array's address once
+ * (hipGetSymbolAddress; make that first call outside a graph capture).
+ *   Returns TS_EWORKSPACE, launching nothing, when
+ *   ts_bin_sort_workspace_bytes(N, out->capacity, tiles) exceeds the array
+ *   (about 3M instances at 3M triangles and 3600 tiles).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero; each call writes
+ * what it reads.
+ */
+#define TS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int ts_bin_sort_noalloc(const ts_proj* proj, int64_t N, const ts_camera* cam, const ts_bins* out,
+                        uint32_t* h_count, hipStream_t stream);
+
+/*
  * Forward compositing (Eq. 1; Sec. 3.1): one 256-thread workgroup per tile,
  * records staged through LDS, per-pixel FP64 edge functions and FP32
  * blending, wavefront-ballot early termination.

@@ -28,9 +28,10 @@ TS_WINDOW_LSE = 2
 TS_BINS_SEGMENTED_SORT = 1
 TS_DENSIFY_OPACITY = 0
 TS_DENSIFY_INV_SIGMA = 1
+TS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
-           "ts_bin_sort", "ts_render_forward", "ts_render_forward_stats",
+           "ts_bin_sort", "ts_bin_sort_noalloc", "ts_render_forward", "ts_render_forward_stats",
            "ts_prune_count_views", "ts_render_backward", "ts_raster_backward",
            "ts_project_backward", "ts_batch_layout", "ts_batch_workspace_bytes",
            "ts_render_forward_batched", "ts_densify_workspace_bytes", "ts_densify_select",
@@ -117,6 +118,8 @@ def load():
     L.ts_project.argtypes = [P, P, P, P, I64, PC, PG, PP, P]
     L.ts_bin_sort.restype = ctypes.c_int
     L.ts_bin_sort.argtypes = [PP, I64, PC, P, ctypes.c_size_t, PB, P, P]
+    L.ts_bin_sort_noalloc.restype = ctypes.c_int
+    L.ts_bin_sort_noalloc.argtypes = [PP, I64, PC, PB, P, P]
     L.ts_render_forward.restype = ctypes.c_int
     L.ts_render_forward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
     L.ts_render_forward_stats.restype = ctypes.c_int
@@ -209,6 +212,14 @@ def ts_bin_sort(proj: ts_proj, N: int, cam: ts_camera, ws, ws_bytes: int, out: t
     hc = None if h_count is None else ctypes.cast(h_count, ctypes.c_void_p)
     _check(load().ts_bin_sort(ctypes.byref(proj), N, ctypes.byref(cam), _ptr(ws), ws_bytes,
                               ctypes.byref(out), hc, stream), "ts_bin_sort")
+
+
+def ts_bin_sort_noalloc(proj: ts_proj, N: int, cam: ts_camera, out: ts_bins, h_count=None,
+                        stream: int = 0):
+    """ts_bin_sort on the library's fixed scratch array (no workspace)."""
+    hc = None if h_count is None else ctypes.cast(h_count, ctypes.c_void_p)
+    _check(load().ts_bin_sort_noalloc(ctypes.byref(proj), N, ctypes.byref(cam), ctypes.byref(out),
+                                      hc, stream), "ts_bin_sort_noalloc")
 
 
 def ts_render_forward(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config, rgb, alpha,

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ts_device.h"
 #include "ts_kernels.h"
@@ -76,6 +77,77 @@ bool bins_ok(const ts_bins* b)
 
 }  // namespace
 
+// Scratch memory of ts_bin_sort_noalloc: a fixed device array in the code
+// object, one copy per GPU, held until the process ends.  In host code its
+// name is only a stand-in: kernels get the device address resolved below.
+static __device__ __align__(256) unsigned char scratch[TS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per
+// device (hipGetSymbolAddress with that device current) and kept.
+int scratch_on_current_device(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "ts_bin_sort_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(TS_EINVAL, "ts_bin_sort_noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "ts_bin_sort_noalloc: hipGetSymbolAddress");
+        if (!p) return fail(TS_EHIP, "ts_bin_sort_noalloc: null scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TS_OK;
+}
+
+int bin_sort(const char* name, const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws,
+             size_t ws_bytes, const ts_bins* out, uint32_t* h_count, hipStream_t stream)
+{
+    char msg[192];
+    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: N out of range", name), msg));
+    if (!cam_ok(cam)) return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: bad camera", name), msg));
+    if (!bins_ok(out)) return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: bad bins", name), msg));
+    if (N > 0 && !proj_ok(proj)) return fail(TS_EINVAL, (snprintf(msg, sizeof msg, "%s: bad projection", name), msg));
+    const int num_tiles = ts_num_tiles(cam->width, cam->height);
+    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, N, out->capacity, num_tiles);
+    if (!ws || ws_bytes < need.bytes)
+        return fail(TS_EWORKSPACE,
+                    (snprintf(msg, sizeof msg, "%s: workspace of %zu bytes needed, %zu available",
+                              name, need.bytes, ws ? ws_bytes : (size_t)0), msg));
+    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, N, out->capacity, num_tiles);
+    bool overflow = false;
+    hipError_t e;
+    if (N == 0) {
+        // empty scene: zero counts and ranges, and a valid tile order
+        ts::launch_fill_u32(out->d_count, 4, 0u, stream);
+        ts::launch_fill_u32(out->ranges, 2 * (int64_t)num_tiles, 0u, stream);
+        ts::launch_tile_order(out->ranges, num_tiles, nullptr, out->order, stream);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, name);
+        if (h_count) {
+            h_count[0] = 0;
+            h_count[1] = 0;
+        }
+        return TS_OK;
+    }
+    e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, N, nullptr, nullptr, 0,
+                         tiles_x_of(cam), num_tiles, w, *out, h_count, &overflow, stream);
+    if (e != hipSuccess) return hip_fail(e, name);
+    if (overflow) return fail(TS_ECAPACITY, (snprintf(msg, sizeof msg, "%s: instances exceed capacity", name), msg));
+    return TS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t ts_proj_record_bytes(void) { return sizeof(ts::TriRecord); }
@@ -113,34 +185,32 @@ int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, 
                 const ts_bins* out, uint32_t* h_count, hipStream_t stream)
 {
     g_msg[0] = 0;
-    if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_bin_sort: N out of range");
-    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_bin_sort: bad camera");
-    if (!bins_ok(out)) return fail(TS_EINVAL, "ts_bin_sort: bad bins");
-    if (N > 0 && !proj_ok(proj)) return fail(TS_EINVAL, "ts_bin_sort: bad projection");
-    const int num_tiles = ts_num_tiles(cam->width, cam->height);
-    const ts::BinWorkspace need = ts::carve_bin_workspace(nullptr, N, out->capacity, num_tiles);
-    if (!ws || ws_bytes < need.bytes) return fail(TS_EWORKSPACE, "ts_bin_sort: workspace too small");
-    const ts::BinWorkspace w = ts::carve_bin_workspace(ws, N, out->capacity, num_tiles);
-    bool overflow = false;
-    hipError_t e;
-    if (N == 0) {
-        // empty scene: zero counts and ranges, and a valid tile order
-        ts::launch_fill_u32(out->d_count, 4, 0u, stream);
-        ts::launch_fill_u32(out->ranges, 2 * (int64_t)num_tiles, 0u, stream);
-        ts::launch_tile_order(out->ranges, num_tiles, nullptr, out->order, stream);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "ts_bin_sort");
-        if (h_count) {
-            h_count[0] = 0;
-            h_count[1] = 0;
+    return bin_sort("ts_bin_sort", proj, N, cam, ws, ws_bytes, out, h_count, stream);
+}
+
+int ts_bin_sort_noalloc(const ts_proj* proj, int64_t N, const ts_camera* cam, const ts_bins* out,
+                        uint32_t* h_count, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (out && cam && N >= 0 && cam->width > 0 && cam->height > 0) {
+        const size_t need =
+            ts::carve_bin_workspace(nullptr, N, out->capacity, ts_num_tiles(cam->width, cam->height))
+                .bytes;
+        if (need > (size_t)TS_NOALLOC_SCRATCH_BYTES) {
+            char msg[192];
+            snprintf(msg, sizeof msg,
+                     "ts_bin_sort_noalloc: %zu bytes of workspace needed for N = %lld, capacity = "
+                     "%llu; the fixed scratch holds %zu",
+                     need, (long long)N, (unsigned long long)out->capacity,
+                     (size_t)TS_NOALLOC_SCRATCH_BYTES);
+            return fail(TS_EWORKSPACE, msg);
         }
-        return TS_OK;
     }
-    e = ts::run_bin_sort(proj->ntiles, proj->depth, proj->rect, N, nullptr, nullptr, 0,
-                         tiles_x_of(cam), num_tiles, w, *out, h_count, &overflow, stream);
-    if (e != hipSuccess) return hip_fail(e, "ts_bin_sort");
-    if (overflow) return fail(TS_ECAPACITY, "ts_bin_sort: instances exceed capacity");
-    return TS_OK;
+    void* base = nullptr;
+    const int rc = scratch_on_current_device(&base);
+    if (rc != TS_OK) return rc;
+    return bin_sort("ts_bin_sort_noalloc", proj, N, cam, base, (size_t)TS_NOALLOC_SCRATCH_BYTES, out,
+                    h_count, stream);
 }
 
 }  // extern "C"

@@ -84,6 +84,14 @@ def test_struct_layouts_match_header():
 def test_argument_checks_need_no_gpu():
     """Validation errors of the training-side entry points return before any
     HIP call: TS_EINVAL / TS_EWORKSPACE on the host alone."""
+    # the allocation-free binning call refuses lists its fixed scratch cannot hold
+    from paper_2505_19175_amd import synth as _s
+    big = B.ts_bins(1, 1, 1, 1, 1 << 30, 1, 1, 0)
+    with pytest.raises(B.TSError) as e:
+        B.ts_bin_sort_noalloc(B.ts_proj(16, 16, 16, 16, 16, 16), 1000,
+                              B.make_camera(_s.identity_camera(128, 128)), big)
+    assert e.value.code == B.TS_EWORKSPACE and "fixed scratch" in str(e.value)
+    assert B.ts_bin_sort_workspace_bytes(3_000_000, 2_500_000, 3600) <= B.TS_NOALLOC_SCRATCH_BYTES
     assert B.ts_densify_workspace_bytes(10) < B.ts_densify_workspace_bytes(10_000)
     assert B.ts_image_loss_workspace_bytes(0, 5) == 0
     assert B.ts_image_loss_workspace_bytes(64, 48) < B.ts_image_loss_workspace_bytes(128, 96)
