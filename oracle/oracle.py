@@ -51,9 +51,11 @@ def _configure(L):
                                   ctypes.c_int, P, ctypes.c_int64, P, P, P, P, P, P, P, P]
     L.oracle_prune_stats.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
                                      ctypes.c_int, P, ctypes.c_int64, P, P, P]
+    L.oracle_render_flip.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, ctypes.c_int,
+                                     ctypes.c_int, P, ctypes.c_int64, P, P, P, P, P, P, P]
     L.oracle_threads.argtypes = []
     for f in (L.oracle_setup, L.oracle_window, L.oracle_sh, L.oracle_render,
-              L.oracle_backward, L.oracle_prune_stats, L.oracle_threads):
+              L.oracle_render_flip, L.oracle_backward, L.oracle_prune_stats, L.oracle_threads):
         f.restype = ctypes.c_int
     return L
 
@@ -193,6 +195,32 @@ def render(scene, cam, cfg, pix: Optional[np.ndarray] = None) -> dict:
         H, W = cam.height, cam.width
         out = {k: (a.reshape(3, H, W) if k == "rgb" else a.reshape(H, W)) for k, a in out.items()}
     return out
+
+
+def render_flip(scene, cam, cfg, pix: np.ndarray, flips: np.ndarray) -> dict:
+    """Forward render of the listed pixels, each with a mask of its
+    near-threshold decisions (alpha against alpha_min, T(1-alpha) against
+    T_min, numbered in walk order) taken the other way.  Both outcomes of
+    such a decision are correct renders (a rounding difference picks one);
+    flips = 0 gives render()'s result.  Returns rgb [3,npix], alpha, depth,
+    T_final and ndec (the number of such decisions met)."""
+    N = scene.n
+    v, o, s, sh = _scene_arrays(scene)
+    pixa = np.ascontiguousarray(pix, np.int64)
+    fl = np.ascontiguousarray(flips, np.uint32)
+    assert fl.shape == pixa.shape
+    npix = pixa.size
+    rgb = np.zeros(3 * npix)
+    alpha = np.zeros(npix)
+    depth = np.zeros(npix)
+    Tf = np.zeros(npix)
+    ndec = np.zeros(npix, np.int32)
+    rc = lib().oracle_render_flip(N, _p(v), _p(o), _p(s), _p(sh), _deg(scene, cfg),
+                                  _p(_cam16(cam)), cam.width, cam.height, _p(_cfg9(cfg)), npix,
+                                  _p(pixa), _p(fl), _p(rgb), _p(alpha), _p(depth), _p(Tf),
+                                  _p(ndec))
+    assert rc == 0
+    return dict(rgb=rgb.reshape(3, npix), alpha=alpha, depth=depth, T_final=Tf, ndec=ndec)
 
 
 def prune_stats(scene, cam, cfg, pix: Optional[np.ndarray] = None) -> dict:

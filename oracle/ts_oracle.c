@@ -422,6 +422,7 @@ typedef struct {
     double C[3], D, T;
     int nfrag;
     int flag;           /* bit0 alpha near alpha_min, bit1 T near T_min, bit2 depth tie */
+    int ndec;           /* decisions taken within a band (bits 0 and 1), in walk order */
     uint64_t hash;      /* discrete state: composited set, argmax edges, clamps, stop */
 } pixout;
 
@@ -435,12 +436,19 @@ static uint64_t fnv(uint64_t h, uint64_t x)
 }
 
 /* frags == NULL: forward only.  Otherwise the composited fragments are
- * stored (capacity cap) and their count returned through *nf. */
-static void shade_pixel(const oscene* S, const ocfg* cfg, double px, double py,
-                        pixout* out, frag* frags, int cap, int* nf)
+ * stored (capacity cap) and their count returned through *nf.
+ *
+ * A decision taken within its band (alpha against alpha_min, T(1 - alpha)
+ * against T_min) could go either way under rounding, and both outcomes are
+ * correct renders of the pixel.  Such decisions are numbered in walk order
+ * (out->ndec counts them); bit d of `flip` takes the other outcome of the
+ * d-th one, so the alternatives a rounding difference can produce are
+ * enumerable. */
+static void shade_pixel_flip(const oscene* S, const ocfg* cfg, double px, double py,
+                             pixout* out, frag* frags, int cap, int* nf, uint32_t flip)
 {
     double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
-    int nfrag = 0, flag = 0;
+    int nfrag = 0, flag = 0, ndec = 0;
     uint64_t h = 1469598103934665603ull;
     float prev_key = -1.0f;
     int have_prev = 0;
@@ -462,14 +470,24 @@ static void shade_pixel(const oscene* S, const ocfg* cfg, double px, double py,
         double a = tr->o * I;
         int clamped = 0;
         if (a > cfg->alpha_max) { a = cfg->alpha_max; clamped = 1; }
-        if (fabs(a - cfg->alpha_min) < cfg->band_alpha) flag |= 1;
-        if (a < cfg->alpha_min) continue;
+        int skip = a < cfg->alpha_min;
+        if (fabs(a - cfg->alpha_min) < cfg->band_alpha) {
+            flag |= 1;
+            if (ndec < 32 && ((flip >> ndec) & 1u)) skip = !skip;
+            ++ndec;
+        }
+        if (skip) continue;
         if (have_prev && (double)tr->key - (double)prev_key <= 2.0 * (double)(nextafterf(prev_key, 1e30f) - prev_key))
             flag |= 4;
         prev_key = tr->key; have_prev = 1;
         double Tn = T * (1.0 - a);
-        if (fabs(Tn - cfg->T_min) < cfg->band_T) flag |= 2;
-        if (Tn < cfg->T_min) {
+        int stop = Tn < cfg->T_min;
+        if (fabs(Tn - cfg->T_min) < cfg->band_T) {
+            flag |= 2;
+            if (ndec < 32 && ((flip >> ndec) & 1u)) stop = !stop;
+            ++ndec;
+        }
+        if (stop) {
             h = fnv(h, ((uint64_t)i << 8) | 0xffu);
             break;
         }
@@ -490,8 +508,15 @@ static void shade_pixel(const oscene* S, const ocfg* cfg, double px, double py,
     out->T = T;
     out->nfrag = nfrag;
     out->flag = flag;
+    out->ndec = ndec;
     out->hash = h;
     if (nf) *nf = nfrag;
+}
+
+static void shade_pixel(const oscene* S, const ocfg* cfg, double px, double py,
+                        pixout* out, frag* frags, int cap, int* nf)
+{
+    shade_pixel_flip(S, cfg, px, py, out, frags, cap, nf, 0u);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -610,6 +635,37 @@ int oracle_render(int N, const double* v, const double* o, const double* sigma,
         if (nfrag) nfrag[p] = po.nfrag;
         if (flag) flag[p] = po.flag;
         if (hash) hash[p] = po.hash;
+    }
+    free_scene(&S);
+    return 0;
+}
+
+/* The same forward on npix listed pixels, each with its own mask of
+ * near-threshold decisions to take the other way (see shade_pixel_flip):
+ * flips[p] for pixel pix[p].  ndec[p] receives the number of such decisions
+ * met on the way (in the flipped walk). */
+int oracle_render_flip(int N, const double* v, const double* o, const double* sigma,
+                       const double* sh, int deg, const double* cam16, int W, int H,
+                       const double* cfg9, int64_t npix, const int64_t* pix,
+                       const uint32_t* flips, double* rgb, double* alpha, double* depth,
+                       double* T_final, int* ndec)
+{
+    ocam cam; ocfg cfg; oscene S;
+    if (!pix || !flips) return -2;
+    load_cam(cam16, W, H, &cam);
+    load_cfg(cfg9, deg, &cfg);
+    if (build_scene(N, v, o, sigma, sh, &cam, &cfg, &S)) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < npix; ++p) {
+        int64_t lin = pix[p];
+        double px = (double)(lin % W) + 0.5, py = (double)(lin / W) + 0.5;
+        pixout po;
+        shade_pixel_flip(&S, &cfg, px, py, &po, NULL, 0, NULL, flips[p]);
+        for (int c = 0; c < 3; ++c) rgb[c * npix + p] = po.C[c];
+        alpha[p] = 1.0 - po.T;
+        depth[p] = po.D;
+        T_final[p] = po.T;
+        if (ndec) ndec[p] = po.ndec;
     }
     free_scene(&S);
     return 0;

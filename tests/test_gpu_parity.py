@@ -130,11 +130,14 @@ def test_grad_workload(sigma):
 # 300k and 3M triangles at 1280x720 (and 1600x1040): sampled pixels
 # ---------------------------------------------------------------------------
 
-def _sampled(scene, cam, cfg, seed, n_pix=4096, max_flag_frac=0.01):
+def _sampled(scene, cam, cfg, seed, n_pix=4096, max_flag_frac=0.01, resolve=False):
     pix = synth.pixel_sample(seed, cam.width, cam.height, n_pix)
     ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    if resolve:     # depth keys bit-exact: a depth tie orders alike on both sides
+        _check_projection(st, scene, cam, cfg)
     ref = O.render(scene, cam, cfg, pix=pix)
-    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref, pix=pix, max_flag_frac=max_flag_frac)
+    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref, pix=pix, max_flag_frac=max_flag_frac,
+                                           resolve=(scene, cam, cfg, True) if resolve else None)
     dC, _, _ = synth.upstream(seed + 1000, cam.width, cam.height)
     dCs = dC.reshape(3, -1)[:, pix] * (ref["flag"] == 0)[None]
     full = np.zeros_like(dC).reshape(3, -1)

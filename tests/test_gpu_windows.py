@@ -21,11 +21,12 @@ pytestmark = pytest.mark.gpu
 
 WINDOWS = [WINDOW_SIGMOID, WINDOW_LSE]
 NAMES = {WINDOW_SIGMOID: "sigmoid", WINDOW_LSE: "lse"}
-# Largest fraction of pixels the oracle may flag (a decision within rounding
-# of alpha_min, T_min or a depth tie).  The sigmoid's long tails put 80-200
-# fragments on a pixel, many of them near the cut-off: up to ~5.4% of the
-# pixels of the sigma = 4 sweep and ~4.7% of the 3M-triangle sample.
-MAX_FLAG = {WINDOW_SIGMOID: 0.08, WINDOW_LSE: 0.01}
+# Largest fraction of pixels left unverified: flagged by the oracle (a
+# decision within rounding of alpha_min, T_min or a depth tie) and not
+# matching any outcome of their near-threshold decisions.  The sigmoid's long
+# tails put 80-200 fragments on a pixel and flag ~5% of them, which the
+# enumeration of both outcomes of each such decision resolves.
+MAX_FLAG = {WINDOW_SIGMOID: 0.01, WINDOW_LSE: 0.01}
 
 
 def _full(scene, cam, cfg, seed, alpha_depth=True):
@@ -33,7 +34,8 @@ def _full(scene, cam, cfg, seed, alpha_depth=True):
     nvis = _check_projection(st, scene, cam, cfg)
     M = _check_bins(st, scene, cam, cfg)
     ref_f = O.render(scene, cam, cfg)
-    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref_f, max_flag_frac=MAX_FLAG[cfg.window])
+    n_ok, n_flag, worst = G.assert_forward(G.to_np(out), ref_f, max_flag_frac=MAX_FLAG[cfg.window],
+                                           resolve=(scene, cam, cfg, True))
     dC, dA, dD = synth.upstream(seed, cam.width, cam.height, alpha_depth, alpha_depth)
     keep = ref_f["flag"] == 0
     dC = dC * keep[None]
@@ -86,7 +88,7 @@ def test_large_workload_sampled(window):
     wl = synth.workload_large()
     cfg = dataclasses.replace(wl.config, window=window)
     st, n_ok, n_flag, worst, s = _sampled(wl.scene, wl.cameras[0], cfg, 31 + window, n_pix=1024,
-                                          max_flag_frac=MAX_FLAG[window])
+                                          max_flag_frac=MAX_FLAG[window], resolve=True)
     print(NAMES[window], st.M, st.N_v, n_ok, n_flag, worst, s)
 
 

@@ -85,8 +85,8 @@ MUTANTS = [
     ("weight without T", "double w = a * T;\n        for (int c = 0; c < 3; ++c) C[c] += w * tr->rgb[c];",
      "double w = a;\n        for (int c = 0; c < 3; ++c) C[c] += w * tr->rgb[c];"),
     ("background dropped", "out->C[c] = C[c] + cfg->bg[c] * T;", "out->C[c] = C[c];"),
-    ("termination test on old T", "if (Tn < cfg->T_min) {", "if (T < cfg->T_min) {"),
-    ("no cut-off skip", "if (a < cfg->alpha_min) continue;", "if (a <= 0.0) continue;"),
+    ("termination test on old T", "int stop = Tn < cfg->T_min;", "int stop = T < cfg->T_min;"),
+    ("no cut-off skip", "int skip = a < cfg->alpha_min;", "int skip = a <= 0.0;"),
     ("no clamp", "if (a > cfg->alpha_max) { a = cfg->alpha_max; clamped = 1; }",
      "if (a > cfg->alpha_max) { clamped = 1; }"),
     ("sh normalisation", "sqrt((2.0 * l + 1.0) / (4.0 * M_PI)", "sqrt((2.0 * l + 1.0) / (2.0 * M_PI)"),
