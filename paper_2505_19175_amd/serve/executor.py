@@ -9,9 +9,13 @@ PlainExecutor    -- the baseline: one view per launch on one stream, the
                     staged pipeline ts_project -> ts_bin_sort (host read of
                     the instance count) -> ts_render_forward, no graph.
 
-With d2h set, either executor also copies each batch's colour images into
-pinned host memory (allocated up front) after the render, and a batch is
-complete once that copy is: latency then includes the transfer to the host.
+Delivery: after the render, on the same stream, each request's frame is
+copied out of the slot's buffers into memory the request owns
+(`Request.result`): (rgb [3,H,W], alpha [H,W], depth [H,W]) device tensors,
+or with d2h set the colour image alone in pinned host memory
+([3,H,W], torch's caching host allocator).  A batch is complete once those
+copies are, so the next batch on the slot can overwrite the slot's buffers
+at once and latency includes handing the frame over.
 """
 from __future__ import annotations
 
@@ -29,6 +33,16 @@ VIEW_BYTES = ctypes.sizeof(B.ts_view)
 
 class _Slot:
     pass
+
+
+def _deliver(rgb, alpha, depth, d2h: bool):
+    """Copies of one view's outputs that the request owns, enqueued on the
+    current stream (the one that rendered them)."""
+    if d2h:
+        host = torch.empty(rgb.shape, dtype=torch.float32, pin_memory=True)
+        host.copy_(rgb, non_blocking=True)
+        return (host, None, None)
+    return (rgb.clone(), alpha.clone(), depth.clone())
 
 
 class BatchedExecutor:
@@ -65,8 +79,6 @@ class BatchedExecutor:
             s.desc_dev = torch.zeros(desc_bytes, dtype=torch.uint8, device=dev)
             s.desc_host = torch.zeros(desc_bytes, dtype=torch.uint8).pin_memory()
             s.count_host = torch.zeros(4, dtype=torch.int32).pin_memory()
-            s.rgb_host = (torch.empty(3 * max_pixels, dtype=torch.float32, pin_memory=True)
-                          if d2h else None)
             s.views = (B.ts_view * max_views)()
             s.proj = B.ts_proj(s.rec.data_ptr(), s.rect.data_ptr(), s.depth_key.data_ptr(),
                                s.ntiles.data_ptr(), None)
@@ -127,8 +139,11 @@ class BatchedExecutor:
                 s.graph.replay()
             else:
                 self._launch(s, s.stream.cuda_stream)
-            if self.d2h:   # the views' colour images are contiguous from offset 0
-                s.rgb_host[: 3 * pixels].copy_(s.rgb[: 3 * pixels], non_blocking=True)
+            for i, r in enumerate(batch):
+                po, W, H = int(views[i].pixel_offset), r.camera.width, r.camera.height
+                r.result = _deliver(s.rgb[3 * po: 3 * po + 3 * W * H].view(3, H, W),
+                                    s.alpha[po: po + W * H].view(H, W),
+                                    s.depth[po: po + W * H].view(H, W), self.d2h)
             s.event.record(s.stream)
             s.count_host.copy_(s.d_count, non_blocking=True)
 
@@ -144,7 +159,8 @@ class BatchedExecutor:
         return res
 
     def outputs(self, slot: int, batch: List[Request]):
-        """Per-request (rgb [3,H,W], alpha, depth) views into the slot's buffers."""
+        """Per-request (rgb [3,H,W], alpha, depth) views into the slot's
+        buffers (valid until the slot's next submission)."""
         s = self._slots[slot]
         views, _, _ = self.layout(batch)
         out = []
@@ -172,23 +188,19 @@ class PlainExecutor:
         self.event = torch.cuda.Event()
         self.batch = None
         self.d2h = d2h
-        self.hosts = {}
 
     def _state(self, W, H):
         key = (W, H)
         if key not in self.states:
             self.states[key] = ViewState(self.N, W, H, self.capacity)
             self.outs[key] = self.states[key].outputs()
-            if self.d2h:
-                self.hosts[key] = torch.empty((3, H, W), dtype=torch.float32, pin_memory=True)
         return self.states[key], self.outs[key]
 
     def submit(self, slot: int, batch: List[Request]) -> None:
         (r,) = batch
         st, out = self._state(r.camera.width, r.camera.height)
         self.ras.forward(st, self.scene_t, r.camera, out=out, sync=True)
-        if self.d2h:
-            self.hosts[(r.camera.width, r.camera.height)].copy_(out.rgb, non_blocking=True)
+        r.result = _deliver(out.rgb, out.alpha, out.depth, self.d2h)
         self.event.record()
         self.batch = batch
         self.last = (st, out)

@@ -3,8 +3,9 @@ resolutions, driven in real time against a Scheduler + executor, with
 latency percentiles and throughput over a measurement window."""
 from __future__ import annotations
 
+import math
 import time
-from typing import Callable, List
+from typing import Callable, List, Optional
 
 import numpy as np
 
@@ -29,9 +30,13 @@ def poisson_requests(rate: float, duration: float, seed: int, sizes=synth.SERVE_
 
 
 def drive(sched: Scheduler, requests: List[Request], clock: Callable[[], float],
-          spin: Callable[[], None] = lambda: None, t0: float = None) -> None:
+          spin: Callable[[], None] = lambda: None, t0: float = None,
+          stop_at: Optional[float] = None) -> None:
     """Feed requests at their arrival times (relative to t0) until every one
-    has completed."""
+    has completed, or, with stop_at (relative to t0), until that time once
+    every request has arrived: a server past saturation then leaves its
+    backlog queued (those requests never complete), while the batches in
+    flight are still collected."""
     if t0 is None:
         t0 = clock()
     for r in requests:
@@ -42,30 +47,48 @@ def drive(sched: Scheduler, requests: List[Request], clock: Callable[[], float],
         while i < len(requests) and requests[i].arrival <= now:
             sched.arrive(requests[i])
             i += 1
+        if stop_at is not None and i == len(requests) and now >= t0 + stop_at:
+            sched.queue.clear()
+            if not sched.in_flight:
+                break
         if not sched.step():
             spin()
 
 
 def summarize(requests: List[Request], t0: float, warmup: float, duration: float) -> dict:
+    """Over the requests that arrived in [warmup, duration): frames/s
+    delivered, and latency percentiles with a request that never completed
+    counted as infinitely late (p99 is then None once more than 1% are
+    missing: the server did not keep up)."""
     win = [r for r in requests if warmup <= r.arrival - t0 < duration]
-    lat = [r.latency * 1e3 for r in win if r.latency is not None]
     if not win:
         return dict(n=0)
+    done = [r for r in win if r.done is not None and not r.failed]
+    lat = [r.latency * 1e3 for r in done] + [math.inf] * (len(win) - len(done))
     t_start = t0 + warmup
-    t_end = max(r.done for r in win)
+    t_end = max((r.done for r in done), default=t_start)
     span = max(t_end - t_start, duration - warmup)
-    return dict(n=len(win), frames_per_s=round(len(win) / span, 2),
-                p50_ms=round(percentile(lat, 50), 3), p99_ms=round(percentile(lat, 99), 3),
-                mean_ms=round(float(np.mean(lat)), 3))
+    fin = lambda x: round(x, 3) if math.isfinite(x) else None
+    return dict(n=len(win), completed=len(done), frames_per_s=round(len(done) / span, 2),
+                p50_ms=fin(percentile(lat, 50)), p99_ms=fin(percentile(lat, 99)),
+                mean_ms=fin(float(np.mean(lat))) if len(done) == len(win) else None)
 
 
-def run_load(make_scheduler: Callable[[], Scheduler], rate: float, duration: float, warmup: float,
-             seed: int) -> dict:
+def drop_frame(r: Request) -> None:
+    """The load generator's consumer: takes the delivered frame and lets it go."""
+    r.result = None
+
+
+def run_load(make_scheduler: Callable[[Callable[[Request], None]], Scheduler], rate: float,
+             duration: float, warmup: float, seed: int, drain: Optional[float] = None) -> dict:
+    """make_scheduler(sink) -> Scheduler.  With drain, requests still queued
+    `drain` seconds after the last arrival are abandoned (see drive)."""
     reqs = poisson_requests(rate, duration, seed)
-    sched = make_scheduler()
+    sched = make_scheduler(drop_frame)
     clock = time.perf_counter
     t0 = clock()
-    drive(sched, reqs, clock, spin=lambda: time.sleep(0), t0=t0)
+    drive(sched, reqs, clock, spin=lambda: time.sleep(0), t0=t0,
+          stop_at=None if drain is None else duration + drain)
     s = summarize(reqs, t0, warmup, duration)
     s.update(rate=rate, batches=len(sched.batches), overflows=sched.overflows,
              mean_views_per_batch=round(float(np.mean([b["views"] for b in sched.batches])), 2)

@@ -13,6 +13,12 @@ estimates stays within `fill` of the executor's capacity, the views fit in
 its slots and the tiles in its tile budget.  instances_per_pixel starts at a
 prior and follows the largest ratio seen in completed batches (times a
 safety margin), so an overflow is rare and is repaired by a retry.
+
+Delivery: the executor writes each request's frame into memory the request
+owns (`Request.result`) before the batch counts as complete, so a slot can
+be refilled at once; `sink(request)` is called for every completed (or
+failed) request inside step(), before any slot is refilled, and is where a
+consumer takes the frame.
 """
 from __future__ import annotations
 
@@ -37,6 +43,8 @@ class Request:
     done: Optional[float] = None
     attempts: int = 0
     failed: bool = False       # too large for the sort buffer even alone
+    result: object = None      # the delivered frame, set by the executor at submission and
+                               # valid once `done` is set (memory the request owns)
 
     @property
     def pixels(self) -> int:
@@ -71,8 +79,10 @@ class Executor(Protocol):
 
 class Scheduler:
     def __init__(self, executor: Executor, clock: Callable[[], float],
-                 instances_per_pixel: float = 0.5, margin: float = 1.25, fill: float = 0.9):
+                 instances_per_pixel: float = 0.5, margin: float = 1.25, fill: float = 0.9,
+                 sink: Optional[Callable[[Request], None]] = None):
         self.ex = executor
+        self.sink = sink
         self.clock = clock
         self.ipp = instances_per_pixel
         self.margin = margin
@@ -128,7 +138,10 @@ class Scheduler:
                     # alone and still too large for the sort buffer: give up
                     batch[0].failed = True
                     batch[0].done = res.done
+                    batch[0].result = None
                     self.failed.append(batch[0])
+                    if self.sink is not None:
+                        self.sink(batch[0])
                     continue
                 for r in reversed(batch):          # back to the front, in order
                     self.queue.appendleft(r)
@@ -136,6 +149,8 @@ class Scheduler:
             for r in batch:
                 r.done = res.done
                 self.completed.append(r)
+                if self.sink is not None:
+                    self.sink(r)
         for slot in range(self.ex.slots):
             if slot in self.in_flight or not self.queue:
                 continue
@@ -159,4 +174,6 @@ def percentile(xs, q):
     s = sorted(xs)
     k = (len(s) - 1) * q / 100.0
     lo, hi = int(math.floor(k)), int(math.ceil(k))
+    if s[lo] == s[hi] or not math.isfinite(s[hi]):
+        return s[hi] if k > lo else s[lo]
     return s[lo] + (s[hi] - s[lo]) * (k - lo)

@@ -103,22 +103,23 @@ def test_short_load_run_completes(soup):
     sc, cfg, st = soup
     ex = BatchedExecutor(st, cfg, time.perf_counter, max_views=4, max_tiles=4 * 8160,
                          max_pixels=4 * 1920 * 1080, capacity=1 << 21, slots=2)
-    s = run_load(lambda: Scheduler(ex, time.perf_counter, instances_per_pixel=0.3), rate=300,
-                 duration=0.6, warmup=0.1, seed=4)
+    s = run_load(lambda sink: Scheduler(ex, time.perf_counter, instances_per_pixel=0.3, sink=sink),
+                 rate=300, duration=0.6, warmup=0.1, seed=4)
     assert s["n"] > 50 and s["overflows"] == 0 and np.isfinite(s["p99_ms"])
     px = PlainExecutor(st, cfg, time.perf_counter)
-    s2 = run_load(lambda: Scheduler(px, time.perf_counter), rate=300, duration=0.6, warmup=0.1,
-                  seed=4)
+    s2 = run_load(lambda sink: Scheduler(px, time.perf_counter, sink=sink), rate=300,
+                  duration=0.6, warmup=0.1, seed=4)
     assert s2["n"] == s["n"] and np.isfinite(s2["p99_ms"])
     print("batched", s, "plain", s2)
 
 
 def test_host_copy_holds_the_images(soup):
-    """With the host copy on, a completed batch's pinned host buffer holds
-    every view's colour image, bit for bit, and the plain executor's host
-    image equals its device image."""
+    """With the host copy on, each request of a completed batch owns a pinned
+    host copy of its colour image, equal bit for bit to the device image, for
+    the batched and the plain executor."""
     sc, cfg, st = soup
     cams = _cams(5, [(640, 360), (320, 200), (1280, 720)])
+    alone = [_alone(st, cfg, c) for c in cams]
     ex = BatchedExecutor(st, cfg, time.perf_counter, max_views=3, max_tiles=3 * 3600,
                          max_pixels=3 * 1280 * 720, capacity=1 << 21, slots=2, d2h=True)
     for k, mix in enumerate([[0, 1, 2], [2, 0], [1]]):
@@ -126,15 +127,54 @@ def test_host_copy_holds_the_images(soup):
         batch = [Request(i, cams[i], 0.0) for i in mix]
         ex.submit(slot, batch)
         _wait(ex, slot)
-        views, _, _ = ex.layout(batch)
-        host = ex._slots[slot].rgb_host.numpy()
-        for j, (i, (rgb, _, _)) in enumerate(zip(mix, ex.outputs(slot, batch))):
-            po, W, H = int(views[j].pixel_offset), cams[i].width, cams[i].height
-            np.testing.assert_array_equal(host[3 * po: 3 * po + 3 * W * H].reshape(3, H, W),
-                                          rgb.cpu().numpy())
+        for i, r in zip(mix, batch):
+            host, a, d = r.result
+            assert host.is_pinned() and a is None and d is None
+            np.testing.assert_array_equal(host.numpy(), alone[i][0])
     px = PlainExecutor(st, cfg, time.perf_counter, d2h=True)
-    cam = cams[1]
-    px.submit(0, [Request(0, cam, 0.0)])
+    r = Request(0, cams[1], 0.0)
+    px.submit(0, [r])
     _wait(px, 0)
-    np.testing.assert_array_equal(px.hosts[(cam.width, cam.height)].numpy(),
-                                  px.outs[(cam.width, cam.height)].rgb.cpu().numpy())
+    np.testing.assert_array_equal(r.result[0].numpy(), alone[1][0])
+
+
+@pytest.mark.parametrize("d2h", [False, True])
+def test_continuous_batching_delivers_every_frame(soup, d2h):
+    """Requests arriving while others are on the GPU: two slots in flight,
+    slots refilled as soon as a batch completes.  Every request's delivered
+    frame (taken by the consumer inside the scheduler step, after its slot
+    may already hold the next batch) equals the same view rendered alone."""
+    sc, cfg, st = soup
+    sizes = [(640, 360), (1280, 720), (320, 200), (1920, 1080), (641, 359), (960, 540)] * 3
+    cams = _cams(6, sizes)
+    ex = BatchedExecutor(st, cfg, time.perf_counter, max_views=3, max_tiles=3 * 8160,
+                         max_pixels=3 * 1920 * 1080, capacity=1 << 21, slots=2, d2h=d2h)
+    got = {}
+
+    def sink(r):
+        rgb, a, d = r.result
+        got[r.rid] = (rgb.cpu().numpy(), None if a is None else a.cpu().numpy(),
+                      None if d is None else d.cpu().numpy())
+        r.result = None
+
+    sched = Scheduler(ex, time.perf_counter, instances_per_pixel=0.3, sink=sink)
+    reqs = [Request(i, c, 0.0) for i, c in enumerate(cams)]
+    # arrivals in three waves: the second and third come while batches run
+    for r in reqs[:6]:
+        sched.arrive(r)
+    sched.step()
+    for r in reqs[6:12]:
+        sched.arrive(r)
+    sched.step()
+    for r in reqs[12:]:
+        sched.arrive(r)
+    while not sched.idle():
+        sched.step()
+    assert len(got) == len(reqs) and sched.overflows == 0
+    assert max(b["views"] for b in sched.batches) > 1
+    for i, c in enumerate(cams):
+        ref = _alone(st, cfg, c)
+        np.testing.assert_array_equal(got[i][0], ref[0])
+        if not d2h:
+            np.testing.assert_array_equal(got[i][1], ref[1])
+            np.testing.assert_array_equal(got[i][2], ref[2])
