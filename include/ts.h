@@ -284,8 +284,13 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
  * separately.  ts_raster_backward accumulates the per-triangle 2D gradients
  * into proj->g2d (which must hold zeros, as the caller's zero fill and
  * every ts_project_backward leave it); ts_project_backward turns them into
- * gv, go, gsigma, gsh and re-zeroes the rows it consumed: call it after
- * every ts_raster_backward.
+ * gv, go, gsigma, gsh and re-zeroes the rows it consumed.
+ * Caller obligation: call ts_project_backward (or ts_project_backward_adam)
+ * on the same proj after every ts_raster_backward, before the next raster
+ * backward or ts_render_backward on that g2d array.  The library keeps a
+ * host-side record of g2d arrays filled and not yet consumed (up to 64 at a
+ * time) and returns TS_EINVAL, launching nothing, for a raster backward on
+ * one of them.
  */
 int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
                        const ts_config* cfg, const float* dL_drgb, const float* dL_dalpha,
@@ -295,6 +300,48 @@ int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera
 int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_proj* proj,
                         const ts_camera* cam, const ts_config* cfg, float* gv, float* go,
                         float* gsigma, float* gsh, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Stored-fragment variant, kept to measure what the recompute backward saves:
+ * the forward keeps every composited fragment (its tile-list entry, alpha
+ * and the transmittance in front of it, 12 bytes) and the backward reads
+ * them instead of recovering transmittance from T_final (Sec. 3.3
+ * gradients; the same arithmetic as ts_render_forward / ts_raster_backward).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of ts_render_forward_count for a width x height view. */
+size_t ts_fragment_workspace_bytes(int32_t width, int32_t height);
+
+/* ts_render_forward that also writes, per pixel, the number of composited
+ * fragments (frag_count [H][W]) and their first slot (frag_offset [H][W], the
+ * exclusive prefix sum in row-major pixel order), and F, their total, into
+ * d_total[0] (device).  TS_EINVAL for a null pointer, TS_EWORKSPACE when
+ * ws_bytes < ts_fragment_workspace_bytes(W, H). */
+int ts_render_forward_count(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                            const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                            float* T_final, uint32_t* last, uint32_t* frag_count,
+                            uint32_t* frag_offset, uint32_t* d_total, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* ts_render_forward that stores every composited fragment of pixel p at
+ * slots frag_offset[p] + 0, 1, ... in blending order (frag_offset from
+ * ts_render_forward_count on the same bins): frag_entry = its index in the
+ * tile's list, frag_alpha, frag_T = transmittance in front of it; arrays of
+ * F entries (device). */
+int ts_render_forward_store(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                            const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                            float* T_final, uint32_t* last, const uint32_t* frag_offset,
+                            uint32_t* frag_entry, float* frag_alpha, float* frag_T,
+                            hipStream_t stream);
+
+/* ts_raster_backward reading the stored fragments (no transmittance
+ * recovery); the same g2d contract as ts_raster_backward. */
+int ts_raster_backward_stored(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                              const ts_config* cfg, const float* dL_drgb, const float* dL_dalpha,
+                              const float* dL_ddepth, const float* T_final, const uint32_t* last,
+                              const uint32_t* frag_count, const uint32_t* frag_offset,
+                              const uint32_t* frag_entry, const float* frag_alpha,
+                              const float* frag_T, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Batched forward rendering of several views of one resident soup (serving).

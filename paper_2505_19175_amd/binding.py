@@ -33,7 +33,8 @@ TS_NOALLOC_SCRATCH_BYTES = 64 << 20
 EXPORTS = ("ts_proj_record_bytes", "ts_num_tiles", "ts_bin_sort_workspace_bytes", "ts_project",
            "ts_bin_sort", "ts_bin_sort_noalloc", "ts_render_forward", "ts_render_forward_stats",
            "ts_prune_count_views", "ts_render_backward", "ts_raster_backward",
-           "ts_project_backward", "ts_batch_layout", "ts_batch_workspace_bytes",
+           "ts_project_backward", "ts_fragment_workspace_bytes", "ts_render_forward_count",
+           "ts_render_forward_store", "ts_raster_backward_stored", "ts_batch_layout", "ts_batch_workspace_bytes",
            "ts_render_forward_batched", "ts_densify_workspace_bytes", "ts_densify_select",
            "ts_densify_subdivide", "ts_image_loss_workspace_bytes", "ts_image_loss",
            "ts_optimizer_step", "ts_project_backward_adam", "ts_error_string",
@@ -133,6 +134,15 @@ def load():
     L.ts_raster_backward.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P]
     L.ts_project_backward.restype = ctypes.c_int
     L.ts_project_backward.argtypes = [P, P, I64, PP, PC, PG, P, P, P, P, P]
+    L.ts_fragment_workspace_bytes.restype = ctypes.c_size_t
+    L.ts_fragment_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.ts_render_forward_count.restype = ctypes.c_int
+    L.ts_render_forward_count.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P, P, P, P,
+                                          ctypes.c_size_t, P]
+    L.ts_render_forward_store.restype = ctypes.c_int
+    L.ts_render_forward_store.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P, P, P, P, P]
+    L.ts_raster_backward_stored.restype = ctypes.c_int
+    L.ts_raster_backward_stored.argtypes = [PP, PB, PC, PG, P, P, P, P, P, P, P, P, P, P, P]
     L.ts_batch_layout.restype = ctypes.c_int
     L.ts_batch_layout.argtypes = [P, ctypes.c_int32, P, P]
     L.ts_batch_workspace_bytes.restype = ctypes.c_size_t
@@ -276,6 +286,41 @@ def ts_project_backward_adam(v, a, b, sh, o, sigma, N: int, proj: ts_proj, cam: 
                                            _ptr(sigma), N, ctypes.byref(proj), ctypes.byref(cam),
                                            ctypes.byref(cfg), ctypes.byref(state),
                                            ctypes.byref(opt), stream), "ts_project_backward_adam")
+
+
+def ts_fragment_workspace_bytes(width: int, height: int) -> int:
+    return int(load().ts_fragment_workspace_bytes(width, height))
+
+
+def ts_render_forward_count(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config, rgb,
+                            alpha, depth, T_final, last, frag_count, frag_offset, d_total, ws,
+                            ws_bytes: int, stream: int = 0):
+    _check(load().ts_render_forward_count(ctypes.byref(proj), ctypes.byref(bins),
+                                          ctypes.byref(cam), ctypes.byref(cfg), _ptr(rgb),
+                                          _ptr(alpha), _ptr(depth), _ptr(T_final), _ptr(last),
+                                          _ptr(frag_count), _ptr(frag_offset), _ptr(d_total),
+                                          _ptr(ws), ws_bytes, stream), "ts_render_forward_count")
+
+
+def ts_render_forward_store(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config, rgb,
+                            alpha, depth, T_final, last, frag_offset, frag_entry, frag_alpha,
+                            frag_T, stream: int = 0):
+    _check(load().ts_render_forward_store(ctypes.byref(proj), ctypes.byref(bins),
+                                          ctypes.byref(cam), ctypes.byref(cfg), _ptr(rgb),
+                                          _ptr(alpha), _ptr(depth), _ptr(T_final), _ptr(last),
+                                          _ptr(frag_offset), _ptr(frag_entry), _ptr(frag_alpha),
+                                          _ptr(frag_T), stream), "ts_render_forward_store")
+
+
+def ts_raster_backward_stored(proj: ts_proj, bins: ts_bins, cam: ts_camera, cfg: ts_config,
+                              dL_drgb, dL_dalpha, dL_ddepth, T_final, last, frag_count,
+                              frag_offset, frag_entry, frag_alpha, frag_T, stream: int = 0):
+    _check(load().ts_raster_backward_stored(ctypes.byref(proj), ctypes.byref(bins),
+                                            ctypes.byref(cam), ctypes.byref(cfg), _ptr(dL_drgb),
+                                            _ptr(dL_dalpha), _ptr(dL_ddepth), _ptr(T_final),
+                                            _ptr(last), _ptr(frag_count), _ptr(frag_offset),
+                                            _ptr(frag_entry), _ptr(frag_alpha), _ptr(frag_T),
+                                            stream), "ts_raster_backward_stored")
 
 
 def ts_batch_layout(views, n: int):

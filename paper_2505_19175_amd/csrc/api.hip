@@ -109,6 +109,35 @@ int scratch_on_current_device(void** out)
     return TS_OK;
 }
 
+// The per-triangle 2D gradient accumulators (ts_proj.g2d) must hold zeros
+// when a raster backward starts; every backward projection consumes them and
+// leaves them zero.  This host-side record of the accumulator arrays a raster
+// backward has filled and no backward projection has consumed yet turns a
+// second raster backward on them into TS_EINVAL instead of a silently summed
+// gradient.
+std::mutex g_g2d_mu;
+const void* g_g2d_pending[64] = {};
+
+bool g2d_pending(const void* g)
+{
+    std::lock_guard<std::mutex> lock(g_g2d_mu);
+    for (const void* q : g_g2d_pending)
+        if (q == g) return true;
+    return false;
+}
+
+void g2d_mark(const void* g, bool pending)
+{
+    std::lock_guard<std::mutex> lock(g_g2d_mu);
+    for (const void*& q : g_g2d_pending) {
+        if (pending && q == nullptr) {
+            q = g;
+            return;
+        }
+        if (!pending && q == g) q = nullptr;
+    }
+}
+
 int bin_sort(const char* name, const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws,
              size_t ws_bytes, const ts_bins* out, uint32_t* h_count, hipStream_t stream)
 {
@@ -287,14 +316,17 @@ int ts_render_backward(const float* v, const float* o, const float* sigma, const
         return fail(TS_EINVAL, "ts_render_backward: null pointer");
     if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_render_backward: null upstream");
     if (N == 0) return TS_OK;
+    if (g2d_pending(proj->g2d))
+        return fail(TS_EINVAL, "ts_render_backward: the 2D gradient accumulators still hold a "
+                               "raster backward (call ts_project_backward first)");
     const ts::Cam k = to_cam(cam);
     const ts::Cfg g = to_cfg(cfg);
     ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, k, g,
                                tiles_x_of(cam), ts_num_tiles(cam->width, cam->height), dL_drgb,
                                dL_dalpha, dL_ddepth, T_final, last, bins->blocks, proj->g2d,
                                stream);
-    ts::launch_backproject(v, proj->cgrad, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go, gsigma,
-                           gsh, stream);
+    ts::launch_backproject(v, proj->cgrad, N, k, g, proj->rect, proj->ntiles, proj->g2d, gv, go,
+                           gsigma, gsh, stream);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_backward");
 }
@@ -309,12 +341,17 @@ int ts_raster_backward(const ts_proj* proj, const ts_bins* bins, const ts_camera
     if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_raster_backward: bad config");
     if (!bins_ok(bins) || !proj_ok(proj)) return fail(TS_EINVAL, "ts_raster_backward: bad state");
     if (!dL_drgb || !T_final || !last) return fail(TS_EINVAL, "ts_raster_backward: null upstream");
+    if (g2d_pending(proj->g2d))
+        return fail(TS_EINVAL, "ts_raster_backward: the 2D gradient accumulators still hold the "
+                               "previous raster backward (call ts_project_backward first)");
     ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
                                to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
                                dL_drgb, dL_dalpha, dL_ddepth, T_final, last, bins->blocks,
                                proj->g2d, stream);
     const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_raster_backward");
+    if (e != hipSuccess) return hip_fail(e, "ts_raster_backward");
+    g2d_mark(proj->g2d, true);
+    return TS_OK;
 }
 
 int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_proj* proj,
@@ -325,13 +362,104 @@ int ts_project_backward(const float* v, const float* sh, int64_t N, const ts_pro
     if (N < 0 || N > 0xffffffffll) return fail(TS_EINVAL, "ts_project_backward: N out of range");
     if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_project_backward: bad camera");
     if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_project_backward: bad config");
-    if (N == 0) return TS_OK;
+    if (N == 0) {
+        if (proj) g2d_mark(proj->g2d, false);
+        return TS_OK;
+    }
     if (!proj_ok(proj) || !proj->cgrad || !v || !sh || !gv || !go || !gsigma || !gsh)
         return fail(TS_EINVAL, "ts_project_backward: null pointer");
     ts::launch_backproject(v, proj->cgrad, N, to_cam(cam), to_cfg(cfg), proj->rect, proj->ntiles,
                            proj->g2d, gv, go, gsigma, gsh, stream);
     const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project_backward");
+    if (e != hipSuccess) return hip_fail(e, "ts_project_backward");
+    g2d_mark(proj->g2d, false);
+    return TS_OK;
+}
+
+size_t ts_fragment_workspace_bytes(int32_t width, int32_t height)
+{
+    if (width <= 0 || height <= 0) return 0;
+    return ts::fragment_scan_workspace_bytes((int64_t)width * height);
+}
+
+int ts_render_forward_count(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                            const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                            float* T_final, uint32_t* last, uint32_t* frag_count,
+                            uint32_t* frag_offset, uint32_t* d_total, void* ws, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_render_forward_count: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_forward_count: bad config");
+    if (!bins_ok(bins) || !proj || !proj->rec)
+        return fail(TS_EINVAL, "ts_render_forward_count: bad projection or bins");
+    if (!rgb || !alpha || !depth || !T_final || !last || !frag_count || !frag_offset || !d_total)
+        return fail(TS_EINVAL, "ts_render_forward_count: null output");
+    const int64_t npix = (int64_t)cam->width * cam->height;
+    if (!ws || ws_bytes < ts::fragment_scan_workspace_bytes(npix))
+        return fail(TS_EWORKSPACE, "ts_render_forward_count: workspace too small");
+    ts::FragStore fs{frag_count, nullptr, nullptr, nullptr, nullptr};
+    ts::launch_raster_forward_fragments(proj->rec, bins->vals, bins->ranges, bins->order,
+                                        to_cam(cam), to_cfg(cfg), tiles_x_of(cam),
+                                        ts_num_tiles(cam->width, cam->height), rgb, alpha, depth,
+                                        T_final, last, bins->blocks, 1, fs, stream);
+    ts::launch_fragment_offsets(frag_count, npix, frag_offset, d_total, ws, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward_count");
+}
+
+int ts_render_forward_store(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                            const ts_config* cfg, float* rgb, float* alpha, float* depth,
+                            float* T_final, uint32_t* last, const uint32_t* frag_offset,
+                            uint32_t* frag_entry, float* frag_alpha, float* frag_T,
+                            hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_render_forward_store: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_render_forward_store: bad config");
+    if (!bins_ok(bins) || !proj || !proj->rec)
+        return fail(TS_EINVAL, "ts_render_forward_store: bad projection or bins");
+    if (!rgb || !alpha || !depth || !T_final || !last || !frag_offset || !frag_entry ||
+        !frag_alpha || !frag_T)
+        return fail(TS_EINVAL, "ts_render_forward_store: null output");
+    ts::FragStore fs{nullptr, frag_offset, frag_entry, frag_alpha, frag_T};
+    ts::launch_raster_forward_fragments(proj->rec, bins->vals, bins->ranges, bins->order,
+                                        to_cam(cam), to_cfg(cfg), tiles_x_of(cam),
+                                        ts_num_tiles(cam->width, cam->height), rgb, alpha, depth,
+                                        T_final, last, bins->blocks, 2, fs, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_render_forward_store");
+}
+
+int ts_raster_backward_stored(const ts_proj* proj, const ts_bins* bins, const ts_camera* cam,
+                              const ts_config* cfg, const float* dL_drgb, const float* dL_dalpha,
+                              const float* dL_ddepth, const float* T_final, const uint32_t* last,
+                              const uint32_t* frag_count, const uint32_t* frag_offset,
+                              const uint32_t* frag_entry, const float* frag_alpha,
+                              const float* frag_T, hipStream_t stream)
+{
+    g_msg[0] = 0;
+    if (!cam_ok(cam)) return fail(TS_EINVAL, "ts_raster_backward_stored: bad camera");
+    if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_raster_backward_stored: bad config");
+    if (!bins_ok(bins) || !proj_ok(proj))
+        return fail(TS_EINVAL, "ts_raster_backward_stored: bad state");
+    if (!dL_drgb || !T_final || !last || !frag_count || !frag_offset || !frag_entry ||
+        !frag_alpha || !frag_T)
+        return fail(TS_EINVAL, "ts_raster_backward_stored: null input");
+    ts::FragStore fs{const_cast<uint32_t*>(frag_count), frag_offset,
+                     const_cast<uint32_t*>(frag_entry), const_cast<float*>(frag_alpha),
+                     const_cast<float*>(frag_T)};
+    if (g2d_pending(proj->g2d))
+        return fail(TS_EINVAL, "ts_raster_backward_stored: the 2D gradient accumulators still "
+                               "hold the previous raster backward (call ts_project_backward first)");
+    ts::launch_raster_backward(proj->rec, bins->vals, bins->ranges, bins->order, to_cam(cam),
+                               to_cfg(cfg), tiles_x_of(cam), ts_num_tiles(cam->width, cam->height),
+                               dL_drgb, dL_dalpha, dL_ddepth, T_final, last, bins->blocks,
+                               proj->g2d, stream, &fs);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ts_raster_backward_stored");
+    g2d_mark(proj->g2d, true);
+    return TS_OK;
 }
 
 int ts_batch_layout(ts_view* views, int32_t n, uint32_t* total_tiles, uint64_t* total_pixels)
@@ -484,7 +612,10 @@ int ts_project_backward_adam(float* v, float* a, float* b, float* sh, float* o, 
     if (!cfg_ok(cfg)) return fail(TS_EINVAL, "ts_project_backward_adam: bad config");
     if (!opt || opt->step < 1 || !st)
         return fail(TS_EINVAL, "ts_project_backward_adam: bad step or null settings");
-    if (N == 0) return TS_OK;
+    if (N == 0) {
+        if (proj) g2d_mark(proj->g2d, false);
+        return TS_OK;
+    }
     if (!proj_ok(proj) || !proj->cgrad || !v || !a || !b || !sh || !o || !sigma || !st->m_v ||
         !st->s_v || !st->m_a || !st->s_a || !st->m_b || !st->s_b || !st->m_sh || !st->s_sh)
         return fail(TS_EINVAL, "ts_project_backward_adam: null pointer");
@@ -499,7 +630,9 @@ int ts_project_backward_adam(float* v, float* a, float* b, float* sh, float* o, 
                                 opt->beta_opacity, opt->beta_size, opt->beta1, opt->beta2, bc1,
                                 bc2, opt->eps, stream);
     const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? TS_OK : hip_fail(e, "ts_project_backward_adam");
+    if (e != hipSuccess) return hip_fail(e, "ts_project_backward_adam");
+    g2d_mark(proj->g2d, false);
+    return TS_OK;
 }
 
 size_t ts_densify_workspace_bytes(int64_t N) { return ts::densify_workspace_bytes(N < 0 ? 0 : N); }

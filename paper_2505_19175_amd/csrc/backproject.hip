@@ -178,7 +178,10 @@ __global__ __launch_bounds__(256) void k_backproject(
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int NSH = 3 * K;
     __shared__ float s_gv[256 * 9];
-    __shared__ float s_y[256 * K];     // SH basis at the view direction
+    // SH basis at the view direction, rows padded to an odd stride so the
+    // per-lane row writes hit distinct LDS banks
+    constexpr int KP = K | 1;
+    __shared__ float s_y[256 * KP];
     __shared__ float s_g[256 * 3];     // dL/drgb where the colour is not clamped
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * 256;
@@ -201,10 +204,11 @@ __global__ __launch_bounds__(256) void k_backproject(
         go[i] = go_;
         gsig[i] = gs_;
     }
+
 #pragma unroll
     for (int a = 0; a < 9; ++a) s_gv[tid * 9 + a] = gvo[a];
 #pragma unroll
-    for (int a = 0; a < K; ++a) s_y[tid * K + a] = yo[a];
+    for (int a = 0; a < K; ++a) s_y[tid * KP + a] = yo[a];
 #pragma unroll
     for (int a = 0; a < 3; ++a) s_g[tid * 3 + a] = go3[a];
     __syncthreads();
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(256) void k_backproject(
 #pragma unroll
                 for (int cq = 0; cq < 4; ++cq) {
                     const int q = q0 + cq, k = q / 3, ch = q - 3 * k;
-                    x[cq] = s_y[t * K + k] * s_g[t * 3 + ch];
+                    x[cq] = s_y[t * KP + k] * s_g[t * 3 + ch];
                 }
                 d4[f] = make_float4(x[0], x[1], x[2], x[3]);
             }
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void k_backproject(
     }
     for (int f = tid; f < n; f += 256) {
         const int t = f / NSH, q = f - t * NSH, k = q / 3, ch = q - 3 * k;
-        dst[f] = s_y[t * K + k] * s_g[t * 3 + ch];
+        dst[f] = s_y[t * KP + k] * s_g[t * 3 + ch];
     }
 }
 
@@ -287,7 +291,8 @@ __global__ __launch_bounds__(256) void k_backproject_adam(
     constexpr int NSH = 3 * K;
     __shared__ float s_v[256 * 9];     // vertex rows before the step
     __shared__ float s_gv[256 * 9];
-    __shared__ float s_y[256 * K];
+    constexpr int KP = K | 1;         // odd row stride: conflict-free row writes
+    __shared__ float s_y[256 * KP];
     __shared__ float s_g[256 * 3];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * 256;
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(256) void k_backproject_adam(
 #pragma unroll
     for (int a = 0; a < 9; ++a) s_gv[tid * 9 + a] = gvo[a];
 #pragma unroll
-    for (int a = 0; a < K; ++a) s_y[tid * K + a] = yo[a];
+    for (int a = 0; a < K; ++a) s_y[tid * KP + a] = yo[a];
 #pragma unroll
     for (int a = 0; a < 3; ++a) s_g[tid * 3 + a] = go3[a];
     if (tid < nt && A.beta_s != 0.f) size_loss_grad(s_v + 9 * tid, s_gv + 9 * tid, A.beta_s, N);
@@ -360,7 +365,7 @@ __global__ __launch_bounds__(256) void k_backproject_adam(
     auto sh_grad = [&](int e, float& lr) {
         const int t = e / NSH, q = e - t * NSH, kk = q / 3, ch = q - 3 * kk;
         lr = q < 3 ? A.lr_dc : A.lr_rest;
-        return s_y[t * K + kk] * s_g[t * 3 + ch];
+        return s_y[t * KP + kk] * s_g[t * 3 + ch];
     };
     if ((NSH & 3) == 0 && aligned16(A.sh + soff, A.m_sh + soff, A.s_sh + soff)) {
         float4* P4 = reinterpret_cast<float4*>(A.sh + soff);

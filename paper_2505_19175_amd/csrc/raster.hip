@@ -308,9 +308,20 @@ struct TileJob {
     uint16_t* blocks;   // per list entry: blocks where it composited (null: not kept)
     float* max_weight;  // pruning statistics (null: not kept): largest T*o per triangle,
     uint32_t* pixels;   // and pixels where it is composited
+    // stored-fragment variant: per pixel the number of composited fragments,
+    // their first slot, and per slot the tile-list entry, alpha and the
+    // transmittance in front of the fragment
+    uint32_t* fcount;
+    const uint32_t* foffs;
+    uint32_t* fentry;
+    float* falpha;
+    float* fT;
 };
 
-template <int WIN, bool ST>
+// FS: 0 plain forward; 1 also counts each pixel's composited fragments
+// (J.fcount); 2 also stores them at J.foffs[pixel] (the stored-fragment
+// variant the recompute backward is measured against).
+template <int WIN, bool ST, int FS = 0>
 __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
                                          const uint32_t* __restrict__ vals, const Cfg& cfg,
                                          const TileJob& J, StageT<WIN, ST>& S)
@@ -323,6 +334,10 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     uint32_t last = 0;
     bool done = !inside;
+    uint32_t fcnt = 0, foff = 0;
+    if constexpr (FS == 2) {
+        if (inside) foff = J.foffs[(int64_t)P.py * J.W + P.px];
+    }
 
     const uint32_t my_bit = 1u << (4 * P.w + P.g);
     const double dxt = (double)(P.px - J.tx * kTile), dyt = (double)(P.py - J.ty * kTile);
@@ -365,6 +380,17 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             const bool comp = contrib && !stop;
             const float wgt = comp ? f.a * T : 0.f;
             const float tw = comp ? T * r.o : 0.f;   // blending weight T*o (pruning)
+            if constexpr (FS != 0) {
+                if (comp) {
+                    if constexpr (FS == 2) {
+                        const uint32_t q = foff + fcnt;
+                        J.fentry[q] = b - start + (uint32_t)j;
+                        J.falpha[q] = f.a;
+                        J.fT[q] = T;
+                    }
+                    ++fcnt;
+                }
+            }
             C0 = fmaf(wgt, r.rgb[0], C0);
             C1 = fmaf(wgt, r.rgb[1], C1);
             C2 = fmaf(wgt, r.rgb[2], C2);
@@ -407,6 +433,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         J.depth[p] = D;
         if (J.T) J.T[p] = T;
         if (J.last) J.last[p] = last;
+        if constexpr (FS == 1) J.fcount[p] = fcnt;
     }
 }
 
@@ -426,6 +453,25 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
               ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last, out_blocks,
               max_weight, pixels};
     fwd_tile(rec, vals, cfg, J, S);
+}
+
+// The forward of the stored-fragment variant: FS = 1 counts the composited
+// fragments of every pixel, FS = 2 stores them (see fwd_tile).
+template <int WIN, int FS>
+__global__ __launch_bounds__(256) void k_raster_fwd_frag(
+    const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
+    int tiles_x, int num_tiles, float* __restrict__ out_rgb, float* __restrict__ out_alpha,
+    float* __restrict__ out_depth, float* __restrict__ out_T, uint32_t* __restrict__ out_last,
+    uint16_t* __restrict__ out_blocks, FragStore fs)
+{
+    __shared__ StageT<WIN, false> S;
+    const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+    if ((unsigned)tile >= (unsigned)num_tiles) return;
+    TileJob J{tile % tiles_x, tile / tiles_x, cam.W, cam.H, ranges[2 * tile],
+              ranges[2 * tile + 1], out_rgb, out_alpha, out_depth, out_T, out_last, out_blocks,
+              nullptr, nullptr, fs.count, fs.offset, fs.entry, fs.alpha, fs.T};
+    fwd_tile<WIN, false, FS>(rec, vals, cfg, J, S);
 }
 
 // Persistent variant over the tiles of several views: each workgroup takes
@@ -514,14 +560,17 @@ __device__ __forceinline__ uint32_t row_max(uint32_t x)
     return x;
 }
 
-template <int WIN>
+// SF: the stored-fragment variant: the composited fragments of each pixel,
+// their alphas and transmittances come from the forward's store (fs) instead
+// of the recomputed cut-off decisions and T_before = T_after / (1 - alpha).
+template <int WIN, bool SF = false>
 __global__ __launch_bounds__(256) void k_raster_bwd(
     const TriRecord* __restrict__ rec, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, Cam cam, Cfg cfg,
     int tiles_x, int num_tiles, const float* __restrict__ dL_drgb,
     const float* __restrict__ dL_dalpha, const float* __restrict__ dL_ddepth,
     const float* __restrict__ T_final, const uint32_t* __restrict__ last_in,
-    const uint16_t* __restrict__ blocks, float* __restrict__ g2d)
+    const uint16_t* __restrict__ blocks, float* __restrict__ g2d, FragStore fs)
 {
     __shared__ StageT<WIN> S;
     __shared__ uint32_t s_max;
@@ -547,6 +596,23 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         g2 = dL_drgb[2 * hw + p];
         gA = dL_dalpha ? dL_dalpha[p] : 0.f;
         gD = dL_ddepth ? dL_ddepth[p] : 0.f;
+    }
+    // stored fragments of the pixel, walked from its last one back: the next
+    // one to meet (entry, alpha, T) is held in registers, its successor loaded
+    // as soon as it is consumed
+    int fcur = -1, flo = 0;
+    uint32_t fe = 0xffffffffu;
+    float fa = 0.f, fTb = 1.f;
+    if constexpr (SF) {
+        if (inside) {
+            flo = (int)fs.offset[p];
+            fcur = flo + (int)fs.count[p] - 1;
+            if (fcur >= flo) {
+                fe = fs.entry[fcur];
+                fa = fs.alpha[fcur];
+                fTb = fs.T[fcur];
+            }
+        }
     }
     // alpha-gradient part that multiplies T_final / (1 - a): dL/dalpha minus
     // the background seen through the remaining transmittance
@@ -598,12 +664,30 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
             const int dx = P.px - r.ax, dy = P.py - r.ay;   // anchor form of the coefficients
             Frag f;
             const bool in = frag_alpha<WIN>(r, dxt, dyt, cfg.alpha_max, f);
-            const bool contrib = j >= 0 && inside && lo_ + (uint32_t)j < my_last && in &&
-                                 f.a >= cfg.alpha_min;
+            bool contrib;
+            float Ti;
+            if constexpr (SF) {
+                contrib = j >= 0 && fcur >= flo && fe == lo_ + (uint32_t)j;
+                if (contrib) {
+                    f.a = fa;
+                    Ti = fTb;
+                    --fcur;
+                    if (fcur >= flo) {
+                        fe = fs.entry[fcur];
+                        fa = fs.alpha[fcur];
+                        fTb = fs.T[fcur];
+                    } else {
+                        fe = 0xffffffffu;
+                    }
+                }
+            } else {
+                contrib = j >= 0 && inside && lo_ + (uint32_t)j < my_last && in &&
+                          f.a >= cfg.alpha_min;
+            }
             if (__ballot(contrib) == 0ull) continue;
 
             const float rom = __builtin_amdgcn_rcpf(1.f - f.a);
-            const float Ti = T * rom;           // transmittance before this fragment
+            if constexpr (!SF) Ti = T * rom;    // transmittance before this fragment
             const float wgt = contrib ? f.a * Ti : 0.f;
             float v[16];
             v[11] = g0 * wgt;
@@ -735,18 +819,54 @@ void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_
                             int num_tiles, const float* dL_drgb, const float* dL_dalpha,
                             const float* dL_ddepth, const float* T_final,
                             const uint32_t* last, const uint16_t* blocks, float* g2d,
-                            hipStream_t stream)
+                            hipStream_t stream, const FragStore* fs)
 {
     const TriRecord* r = reinterpret_cast<const TriRecord*>(rec);
+    const FragStore none{};
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(num_tiles), dim3(kBlock), 0, stream, r, vals, ranges, order,
                            cam, cfg, tiles_x, num_tiles, dL_drgb, dL_dalpha, dL_ddepth, T_final,
-                           last, blocks, g2d);
+                           last, blocks, g2d, fs ? *fs : none);
     };
+    if (fs) {
+        switch (cfg.window) {
+        case TS_WINDOW_SIGMOID: go(k_raster_bwd<TS_WINDOW_SIGMOID, true>); break;
+        case TS_WINDOW_LSE: go(k_raster_bwd<TS_WINDOW_LSE, true>); break;
+        default: go(k_raster_bwd<TS_WINDOW_PAPER, true>); break;
+        }
+        return;
+    }
     switch (cfg.window) {
     case TS_WINDOW_SIGMOID: go(k_raster_bwd<TS_WINDOW_SIGMOID>); break;
     case TS_WINDOW_LSE: go(k_raster_bwd<TS_WINDOW_LSE>); break;
     default: go(k_raster_bwd<TS_WINDOW_PAPER>); break;
+    }
+}
+
+void launch_raster_forward_fragments(const void* rec, const uint32_t* vals,
+                                     const uint32_t* ranges, const uint32_t* order,
+                                     const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
+                                     float* rgb, float* alpha, float* depth, float* T_final,
+                                     uint32_t* last, uint16_t* blocks, int mode,
+                                     const FragStore& fs, hipStream_t stream)
+{
+    const TriRecord* r = reinterpret_cast<const TriRecord*>(rec);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(num_tiles), dim3(kBlock), 0, stream, r, vals, ranges, order,
+                           cam, cfg, tiles_x, num_tiles, rgb, alpha, depth, T_final, last, blocks,
+                           fs);
+    };
+    const bool store = mode == 2;
+    switch (cfg.window) {
+    case TS_WINDOW_SIGMOID:
+        store ? go(k_raster_fwd_frag<TS_WINDOW_SIGMOID, 2>) : go(k_raster_fwd_frag<TS_WINDOW_SIGMOID, 1>);
+        break;
+    case TS_WINDOW_LSE:
+        store ? go(k_raster_fwd_frag<TS_WINDOW_LSE, 2>) : go(k_raster_fwd_frag<TS_WINDOW_LSE, 1>);
+        break;
+    default:
+        store ? go(k_raster_fwd_frag<TS_WINDOW_PAPER, 2>) : go(k_raster_fwd_frag<TS_WINDOW_PAPER, 1>);
+        break;
     }
 }
 

@@ -135,12 +135,43 @@ void launch_raster_forward_queue(const void* rec, const uint32_t* vals, const ui
                                  uint32_t* queue, int workgroups, float* rgb, float* alpha,
                                  float* depth, hipStream_t stream);
 
+// Stored-fragment variant (the memory form the recompute backward is
+// measured against): per pixel the number of composited fragments and the
+// first slot of its run; per slot the tile-list entry, alpha and the
+// transmittance in front of the fragment.
+struct FragStore {
+    uint32_t* count;
+    const uint32_t* offset;
+    uint32_t* entry;
+    float* alpha;
+    float* T;
+};
+
+// fs == nullptr: the recompute backward (transmittance recovered from
+// T_final); otherwise each pixel's fragments, alphas and transmittances are
+// read from *fs (written by the forward in mode 2 on the same bins).
 void launch_raster_backward(const void* rec, const uint32_t* vals, const uint32_t* ranges,
                             const uint32_t* order, const Cam& cam, const Cfg& cfg, int tiles_x,
                             int num_tiles,
                             const float* dL_drgb, const float* dL_dalpha,
                             const float* dL_ddepth, const float* T_final,
                             const uint32_t* last, const uint16_t* blocks, float* g2d,
-                            hipStream_t stream);
+                            hipStream_t stream, const FragStore* fs = nullptr);
+
+// The forward of the stored-fragment variant: mode 1 writes fs.count, mode 2
+// stores the fragments at fs.offset (an exclusive scan of the counts).
+void launch_raster_forward_fragments(const void* rec, const uint32_t* vals,
+                                     const uint32_t* ranges, const uint32_t* order,
+                                     const Cam& cam, const Cfg& cfg, int tiles_x, int num_tiles,
+                                     float* rgb, float* alpha, float* depth, float* T_final,
+                                     uint32_t* last, uint16_t* blocks, int mode,
+                                     const FragStore& fs, hipStream_t stream);
+
+// offset[p] = sum of count[0..p), total[0] = sum of all (one pass of block
+// sums, one scan of them, one pass applying them); ws of
+// fragment_scan_workspace_bytes(n) bytes.
+size_t fragment_scan_workspace_bytes(int64_t n);
+void launch_fragment_offsets(const uint32_t* count, int64_t n, uint32_t* offset, uint32_t* total,
+                             void* ws, hipStream_t stream);
 
 }  // namespace ts

@@ -162,6 +162,61 @@ class Rasterizer:
         return grads
 
 
+class StoredFragments:
+    """The stored-fragment variant of one view (kept to measure the memory
+    the recompute backward saves): a counting forward, then a forward that
+    keeps every composited fragment (tile-list entry, alpha, transmittance
+    in front of it: 12 bytes each), and a backward that reads them."""
+
+    def __init__(self, ras: "Rasterizer", st: ViewState):
+        self.ras, self.st = ras, st
+        dev, H, W = st.device, st.H, st.W
+        self.count = torch.empty((H, W), dtype=torch.int32, device=dev)
+        self.offset = torch.empty((H, W), dtype=torch.int32, device=dev)
+        self.total = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_bytes = B.ts_fragment_workspace_bytes(W, H)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.entry = self.alpha = self.T = None
+        self.F = 0
+
+    def forward(self, scene_t, cam, out: Optional[Outputs] = None) -> Outputs:
+        """Project, bin, count, size the fragment arrays (one host read of
+        F), then the storing forward."""
+        st, ras = self.st, self.ras
+        ccam = ras.project(st, scene_t, cam)
+        ras.bin_sort(st, ccam, sync=True)
+        st.ccam = ccam
+        if out is None:
+            out = st.outputs()
+        B.ts_render_forward_count(st.proj, st.bins, ccam, ras.ccfg, out.rgb, out.alpha, out.depth,
+                                  out.T_final, out.last, self.count, self.offset, self.total,
+                                  self.ws, self.ws_bytes, _stream())
+        F = int(self.total.item())
+        if self.entry is None or self.entry.numel() < max(F, 1):
+            n = max(F, 1)
+            self.entry = torch.empty(n, dtype=torch.int32, device=st.device)
+            self.alpha = torch.empty(n, dtype=torch.float32, device=st.device)
+            self.T = torch.empty(n, dtype=torch.float32, device=st.device)
+        self.F = F
+        B.ts_render_forward_store(st.proj, st.bins, ccam, ras.ccfg, out.rgb, out.alpha, out.depth,
+                                  out.T_final, out.last, self.offset, self.entry, self.alpha,
+                                  self.T, _stream())
+        return out
+
+    def backward(self, scene_t, out: Outputs, dC, dA=None, dD=None, grads=None):
+        st, ras = self.st, self.ras
+        v, o, sigma, sh = scene_t
+        if grads is None:
+            grads = (torch.empty_like(v), torch.empty_like(o), torch.empty_like(sigma),
+                     torch.empty_like(sh))
+        gv, go, gs, gsh = grads
+        B.ts_raster_backward_stored(st.proj, st.bins, st.ccam, ras.ccfg, dC, dA, dD, out.T_final,
+                                    out.last, self.count, self.offset, self.entry, self.alpha,
+                                    self.T, _stream())
+        B.ts_project_backward(v, sh, st.N, st.proj, st.ccam, ras.ccfg, gv, go, gs, gsh, _stream())
+        return grads
+
+
 def scene_to_device(scene, device="cuda"):
     """Float32 contiguous device copies (v, o, sigma, sh) of a synth.Scene."""
     return tuple(torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()

@@ -493,3 +493,31 @@ def test_abi_rejects_bad_arguments():
     with pytest.raises(B.TSError) as e:
         B.ts_project(*sct, sc.n, B.make_camera(big), B.make_config(cfg), st.proj)
     assert e.value.code == B.TS_EINVAL
+
+
+def test_raster_backward_twice_without_projection_is_rejected(small):
+    """The 2D gradient accumulators of a raster backward must be consumed by
+    a backward projection before the next raster backward: a second one is
+    refused (TS_EINVAL) instead of summing into them, and the pair order
+    then works again."""
+    scene, cam, cfg, seed = small
+    ras, st, sct, out = G.gpu_forward(scene, cam, cfg)
+    dC, _, _ = synth.upstream(seed, cam.width, cam.height)
+    dCt = torch.tensor(dC, device="cuda:0")
+    args = (st.proj, st.bins, st.ccam, ras.ccfg, dCt, None, None, out.T_final, out.last)
+    B.ts_raster_backward(*args)
+    with pytest.raises(B.TSError) as e:
+        B.ts_raster_backward(*args)
+    assert e.value.code == B.TS_EINVAL
+    grads = [torch.empty_like(t) for t in sct]
+    with pytest.raises(B.TSError) as e:
+        B.ts_render_backward(*sct, st.N, st.proj, st.bins, st.ccam, ras.ccfg, dCt, None, None,
+                             out.T_final, out.last, *grads)
+    assert e.value.code == B.TS_EINVAL
+    B.ts_project_backward(sct[0], sct[3], st.N, st.proj, st.ccam, ras.ccfg, *grads)
+    first = [g.clone() for g in grads]
+    B.ts_raster_backward(*args)
+    B.ts_project_backward(sct[0], sct[3], st.N, st.proj, st.ccam, ras.ccfg, *grads)
+    torch.cuda.synchronize()
+    G.assert_grads({k: g.cpu().numpy().astype(np.float64) for k, g in zip(("v", "o", "sigma", "sh"), grads)},
+                   {k: g.cpu().numpy().astype(np.float64) for k, g in zip(("v", "o", "sigma", "sh"), first)})
