@@ -129,51 +129,6 @@ __global__ __launch_bounds__(256) void k_count(const uint32_t* __restrict__ ntil
     }
 }
 
-// Exclusive scan in place of the per-block sums (one workgroup).  The number
-// of blocks is nblocks(n) with n = *d_n (or n_host when d_n is null).  The
-// total goes to total_out[0]; min(total, cap) goes to cap_out[0] and
-// total > cap sets flag_out[0]; the plain sum of sum_blk goes to sum_out[0].
-__global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
-                                                     const uint32_t* __restrict__ d_n,
-                                                     int64_t n_host, uint32_t* total_out,
-                                                     uint32_t* cap_out, uint64_t cap,
-                                                     uint32_t* flag_out,
-                                                     const uint32_t* __restrict__ sum_blk,
-                                                     uint32_t* sum_out)
-{
-    __shared__ uint32_t s_tmp[4];
-    const int64_t n = d_n ? (int64_t)*d_n : n_host;
-    const int64_t nb = nblocks(n);
-    uint32_t running = 0, other = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += kBlock * 4) {
-        uint32_t x[4], s = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t j = c0 + threadIdx.x * 4 + r;
-            x[r] = j < nb ? blk[j] : 0u;
-            s += x[r];
-            other += j < nb ? sum_blk[j] : 0u;
-        }
-        uint32_t tot;
-        uint32_t pre = block_exclusive_scan(s, tot, s_tmp) + running;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t j = c0 + threadIdx.x * 4 + r;
-            if (j < nb) blk[j] = pre;
-            pre += x[r];
-        }
-        running += tot;
-    }
-    uint32_t other_tot;
-    block_exclusive_scan(other, other_tot, s_tmp);
-    if (threadIdx.x == 0) {
-        total_out[0] = running;
-        cap_out[0] = (uint64_t)running > cap ? (uint32_t)cap : running;
-        flag_out[0] = (uint64_t)running > cap ? 1u : 0u;
-        sum_out[0] = other_tot;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // 2. instances in index order
 // ---------------------------------------------------------------------------
@@ -181,21 +136,41 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ blk,
 // by slot by consecutive lanes (coalesced): slot q finds its entry by a
 // binary search over the per-thread prefix counts, then a walk over that
 // thread's kItems entries, and its tile from the entry's tile rectangle.
+// The block's first output slot is the sum of the counts of the blocks before
+// it (k_count's per-block totals, summed here by each block: no separate scan
+// launch); the last block also writes the totals: M, min(M, capacity) for the
+// sort, the overflow flag and N_v.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntiles,
                                               const short4* __restrict__ rect, int64_t N_host,
                                               const uint32_t* __restrict__ d_n,
-                                              const uint32_t* __restrict__ blk, int tiles_x,
+                                              const uint32_t* __restrict__ blk,
+                                              const uint32_t* __restrict__ blk_vis, int tiles_x,
                                               const ts_view* __restrict__ views, int64_t per_view,
                                               uint64_t capacity, uint32_t* __restrict__ tk,
-                                              uint32_t* __restrict__ tv)
+                                              uint32_t* __restrict__ tv, uint32_t* __restrict__ d_M,
+                                              uint32_t* __restrict__ d_sortn,
+                                              uint32_t* __restrict__ d_ovf,
+                                              uint32_t* __restrict__ d_Nv)
 {
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_pre[kBlock];         // instances before each thread's entries
     __shared__ uint32_t s_cnt[kChunk];         // tiles of every entry of the block
     const int64_t N = d_n ? (int64_t)*d_n : N_host;
-    if ((int64_t)blockIdx.x >= nblocks(N)) return;
+    const int64_t nb = nblocks(N);
+    if (nb == 0) {   // nothing to emit: the totals are zero
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *d_M = 0u; *d_sortn = 0u; *d_ovf = 0u; *d_Nv = 0u;
+        }
+        return;
+    }
+    if ((int64_t)blockIdx.x >= nb) return;
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const bool last_block = (int64_t)blockIdx.x == nb - 1;
+    uint32_t before = 0, vis = 0;
+    for (int64_t b = tid; b < (int64_t)blockIdx.x; b += kBlock) before += blk[b];
+    if (last_block)
+        for (int64_t b = tid; b < nb; b += kBlock) vis += blk_vis[b];
     uint32_t c = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -204,10 +179,21 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
         s_cnt[tid * kItems + r] = n;
         c += n;
     }
-    uint32_t tot;
+    uint32_t tot, out0_32, vis_tot;
     s_pre[tid] = block_exclusive_scan(c, tot, s_tmp);
+    block_exclusive_scan(before, out0_32, s_tmp);
+    if (last_block) {
+        block_exclusive_scan(vis, vis_tot, s_tmp);
+        if (tid == 0) {
+            const uint64_t M = (uint64_t)out0_32 + tot;
+            *d_M = (uint32_t)M;
+            *d_sortn = M > capacity ? (uint32_t)capacity : (uint32_t)M;
+            *d_ovf = M > capacity ? 1u : 0u;
+            *d_Nv = vis_tot;
+        }
+    }
     __syncthreads();
-    const uint64_t out0 = (uint64_t)blk[blockIdx.x];
+    const uint64_t out0 = (uint64_t)out0_32;
     for (uint32_t q = tid; q < tot; q += kBlock) {
         if (out0 + q >= capacity) break;
         int t = 0;   // last thread whose first instance is at or before q
@@ -1135,8 +1121,11 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     // 1. tile counts of the N (or *d_n) entries in index order; ranges cleared
     hipLaunchKernelGGL(k_count, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, N, d_n,
                        ws.blk, ws.blk_vis, out.ranges, 2 * (int64_t)num_tiles);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, stream, ws.blk, d_n, N, d_M,
-                       d_sortn, out.capacity, d_ovf, (const uint32_t*)ws.blk_vis, d_Nv);
+    // 2. instances in index order (up to capacity), and the totals
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)(nbN > 0 ? nbN : 1)), dim3(kBlock), 0, stream,
+                       ntiles, reinterpret_cast<const short4*>(rect), N, d_n,
+                       (const uint32_t*)ws.blk, (const uint32_t*)ws.blk_vis, tiles_x, views,
+                       per_view, out.capacity, ws.tk[0], ws.tv[0], d_M, d_sortn, d_ovf, d_Nv);
     int64_t m_max = (int64_t)out.capacity;
     if (h_count) {
         hipError_t err = hipMemcpyAsync(h_count, out.d_count, 2 * sizeof(uint32_t),
@@ -1154,10 +1143,6 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
         }
         m_max = h_count[0];
     }
-    // 2. instances in index order
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles,
-                       reinterpret_cast<const short4*>(rect), N, d_n, ws.blk, tiles_x, views,
-                       per_view, out.capacity, ws.tk[0], ws.tv[0]);
     // 3. stable sort by tile, ranges, longest-first tile order
     hipError_t err = radix_sort(ws.tk[0], ws.tv[0], ws.tk[1], ws.tv[1], ws.tfin, out.vals,
                                 d_sortn, m_max, bits_for(num_tiles), ws, stream);
