@@ -7,8 +7,8 @@
 //   1. count the tiles of every triangle, in index order, and scan the counts
 //   2. emit one instance per (triangle, tile) in index order
 //   3. stable LSD radix sort of the instances by tile id,
-//      ceil(log2 tiles / 8) passes over M; inside a tile the triangles are
-//      still in index order
+//      ceil(log2 tiles / 8) passes over M with the bits split evenly between
+//      them; inside a tile the triangles are still in index order
 //   4. one workgroup per tile sorts that tile's entries by depth key with a
 //      stable radix sort (one wave in registers up to 1024 entries, four
 //      waves and a merge up to 4096, two global ping-pong buffers beyond),
@@ -113,12 +113,22 @@ __global__ __launch_bounds__(256) void k_count(const uint32_t* __restrict__ ntil
     if ((int64_t)blockIdx.x >= nblocks(N)) return;
     const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x * kItems;
     uint32_t c = 0, v = 0;
+    if (base + kItems <= N && (reinterpret_cast<uintptr_t>(ntiles + base) & 15u) == 0u) {
+        const uint4* p4 = reinterpret_cast<const uint4*>(ntiles + base);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r;
-        const uint32_t n = i < N ? ntiles[i] : 0u;
-        c += n;
-        v += n != 0u ? 1u : 0u;
+        for (int r = 0; r < kItems / 4; ++r) {
+            const uint4 q = p4[r];
+            c += q.x + q.y + q.z + q.w;
+            v += (q.x != 0u) + (q.y != 0u) + (q.z != 0u) + (q.w != 0u);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t i = base + r;
+            const uint32_t n = i < N ? ntiles[i] : 0u;
+            c += n;
+            v += n != 0u ? 1u : 0u;
+        }
     }
     uint32_t tot, tot_vis;
     block_exclusive_scan(c, tot, s_tmp);
@@ -154,7 +164,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
 {
     __shared__ uint32_t s_tmp[4];
     __shared__ uint32_t s_pre[kBlock];         // instances before each thread's entries
-    __shared__ uint32_t s_cnt[kChunk];         // tiles of every entry of the block
+    __shared__ uint32_t s_cnt[kChunk];         // tiles of entry tid * kItems + r at r * kBlock + tid
     const int64_t N = d_n ? (int64_t)*d_n : N_host;
     const int64_t nb = nblocks(N);
     if (nb == 0) {   // nothing to emit: the totals are zero
@@ -172,12 +182,26 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
     if (last_block)
         for (int64_t b = tid; b < nb; b += kBlock) vis += blk_vis[b];
     uint32_t c = 0;
+    const int64_t e0 = base + tid * kItems;
+    if (e0 + kItems <= N && (reinterpret_cast<uintptr_t>(ntiles + e0) & 15u) == 0u) {
+        const uint4* p4 = reinterpret_cast<const uint4*>(ntiles + e0);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + tid * kItems + r;
-        const uint32_t n = i < N ? ntiles[i] : 0u;
-        s_cnt[tid * kItems + r] = n;
-        c += n;
+        for (int r = 0; r < kItems / 4; ++r) {
+            const uint4 q = p4[r];
+            s_cnt[(4 * r + 0) * kBlock + tid] = q.x;
+            s_cnt[(4 * r + 1) * kBlock + tid] = q.y;
+            s_cnt[(4 * r + 2) * kBlock + tid] = q.z;
+            s_cnt[(4 * r + 3) * kBlock + tid] = q.w;
+            c += q.x + q.y + q.z + q.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t i = e0 + r;
+            const uint32_t n = i < N ? ntiles[i] : 0u;
+            s_cnt[r * kBlock + tid] = n;
+            c += n;
+        }
     }
     uint32_t tot, out0_32, vis_tot;
     s_pre[tid] = block_exclusive_scan(c, tot, s_tmp);
@@ -202,8 +226,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
             if (s_pre[t + step] <= q) t += step;
         uint32_t k = q - s_pre[t];
         int r = 0;
-        while (k >= s_cnt[t * kItems + r]) {   // ends within the thread's entries
-            k -= s_cnt[t * kItems + r];
+        while (k >= s_cnt[r * kBlock + t]) {   // ends within the thread's entries
+            k -= s_cnt[r * kBlock + t];
             ++r;
         }
         const uint32_t e = (uint32_t)(base + t * kItems + r);
@@ -223,26 +247,29 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ntile
 }
 
 // ---------------------------------------------------------------------------
-// 3. stable LSD radix sort pass (8-bit digit at `shift`)
+// 3. stable LSD radix sort pass (digit of `dbits` <= 8 bits at `shift`)
 // ---------------------------------------------------------------------------
+// The passes split the key's bits evenly (12 bits of tile id: two 6-bit
+// digits), so a block's keys fall into fewer, longer runs.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ d_n, int shift,
-                                                    uint32_t* __restrict__ hist,
+                                                    int dbits, uint32_t* __restrict__ hist,
                                                     int64_t stride)
 {
     __shared__ uint32_t h[kRadix];
     const int64_t n = *d_n;
     const int64_t b = blockIdx.x;
     if (b >= nblocks(n)) return;
+    const uint32_t mask = (1u << dbits) - 1u;
     h[threadIdx.x] = 0u;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t i = b * kChunk + r * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xffu], 1u);
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * stride + b] = h[threadIdx.x];
+    if (threadIdx.x <= mask) hist[threadIdx.x * stride + b] = h[threadIdx.x];
 }
 
 // One workgroup per digit: exclusive scan of that digit's row of block counts.
@@ -277,25 +304,34 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
 
 // Stable scatter.  Keys of a block are read striped (key r*256 + tid), so the
 // stable order inside the block is (round, wave, lane).  Each wave finds the
-// lanes sharing its digit with 8 ballots; per (round, wave, digit) counts in
-// LDS are scanned per digit to give every key its rank.
+// lanes sharing its digit with dbits ballots; per (round, wave, digit) counts
+// in LDS are scanned per digit to give every key its rank.  The block's keys
+// are first placed in LDS in their sorted order, then written out by
+// consecutive lanes, so a store instruction covers a few runs of consecutive
+// addresses instead of up to 64 scattered words.
 __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n,
-    int shift, const uint32_t* __restrict__ hist, int64_t stride,
+    int shift, int dbits, const uint32_t* __restrict__ hist, int64_t stride,
     const uint32_t* __restrict__ dtot)
 {
-    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_off[kRadix];   // output position of the block's k-th key of digit d: s_off[d] + k
+    __shared__ uint32_t s_lst[kRadix];   // first LDS slot of digit d
     __shared__ uint16_t s_cnt[kItems * 4][kRadix];
+    __shared__ uint32_t s_key[kChunk];
+    __shared__ uint32_t s_val[kChunk];
     __shared__ uint32_t s_tmp[4];
     const int64_t n = *d_n;
     const int64_t b = blockIdx.x;
     if (b >= nblocks(n)) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t mask = (1u << dbits) - 1u;
+    const int nloc = (int)min<int64_t>(kChunk, n - b * kChunk);
 
     uint32_t tot;
-    const uint32_t dpre = block_exclusive_scan(dtot[tid], tot, s_tmp);
-    s_base[tid] = dpre + hist[tid * stride + b];
+    const bool dig = (uint32_t)tid <= mask;
+    const uint32_t dpre = block_exclusive_scan(dig ? dtot[tid] : 0u, tot, s_tmp);
+    const uint32_t gbase = dig ? dpre + hist[tid * stride + b] : 0u;
 #pragma unroll
     for (int s = 0; s < kItems * 4; ++s) s_cnt[s][tid] = 0;
     __syncthreads();
@@ -304,40 +340,54 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t i = b * kChunk + r * kBlock + tid;
-        const bool ok = i < n;
-        key[r] = ok ? kin[i] : 0u;
-        val[r] = ok ? vin[i] : 0u;
-        const uint32_t d = (key[r] >> shift) & 0xffu;
+        const int j = r * kBlock + tid;
+        const bool ok = j < nloc;
+        key[r] = ok ? kin[b * kChunk + j] : 0u;
+        val[r] = ok ? vin[b * kChunk + j] : 0u;
+        const uint32_t d = (key[r] >> shift) & mask;
         uint64_t m = __ballot(ok);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            const bool set = (d >> bit) & 1u;
-            const uint64_t bal = __ballot(set);
-            m &= set ? bal : ~bal;
+            if (bit < dbits) {   // the same for the whole block
+                const bool set = (d >> bit) & 1u;
+                const uint64_t bal = __ballot(set);
+                m &= set ? bal : ~bal;
+            }
         }
         rank[r] = (uint32_t)__popcll(m & lt);
         if (ok && (m & lt) == 0ull) s_cnt[r * 4 + w][d] = (uint16_t)__popcll(m);
     }
     __syncthreads();
-    {
-        uint32_t run = 0;
+    uint32_t run = 0;
 #pragma unroll
-        for (int s = 0; s < kItems * 4; ++s) {
-            const uint32_t c = s_cnt[s][tid];
-            s_cnt[s][tid] = (uint16_t)run;
-            run += c;
+    for (int s = 0; s < kItems * 4; ++s) {
+        const uint32_t c = s_cnt[s][tid];
+        s_cnt[s][tid] = (uint16_t)run;
+        run += c;
+    }
+    uint32_t btot;
+    const uint32_t lstart = block_exclusive_scan(run, btot, s_tmp);   // barriers inside
+    s_lst[tid] = lstart;
+    s_off[tid] = gbase - lstart;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (r * kBlock + tid < nloc) {
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t q = s_lst[d] + s_cnt[r * 4 + w][d] + rank[r];
+            s_key[q] = key[r];
+            s_val[q] = val[r];
         }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t i = b * kChunk + r * kBlock + tid;
-        if (i < n) {
-            const uint32_t d = (key[r] >> shift) & 0xffu;
-            const uint32_t pos = s_base[d] + s_cnt[r * 4 + w][d] + rank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+        const int j = r * kBlock + tid;
+        if (j < nloc) {
+            const uint32_t k = s_key[j];
+            const uint32_t pos = s_off[(k >> shift) & mask] + (uint32_t)j;
+            kout[pos] = k;
+            vout[pos] = s_val[j];
         }
     }
 }
@@ -1078,21 +1128,22 @@ static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
                              hipStream_t stream)
 {
     const int passes = (bits + 7) / 8;
+    const int dbits = (bits + passes - 1) / passes;   // <= 8: the bits split evenly
     const int64_t nb = nblocks(n_max > 0 ? n_max : 1);
     uint32_t* ks[2] = {k0, k1};
     uint32_t* vs[2] = {v0, v1};
     int src = 0;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = dbits * p;
         const bool last = p == passes - 1;
         uint32_t* ko = last ? kfin : ks[src ^ 1];
         uint32_t* vo = last ? vfin : vs[src ^ 1];
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, stream, ks[src], d_n,
-                           shift, ws.hist, ws.hist_stride);
-        hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kBlock), 0, stream, ws.hist, d_n,
+                           shift, dbits, ws.hist, ws.hist_stride);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1u << dbits), dim3(kBlock), 0, stream, ws.hist, d_n,
                            ws.hist_stride, ws.dtot);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, stream, ks[src],
-                           vs[src], ko, vo, d_n, shift, ws.hist, ws.hist_stride, ws.dtot);
+                           vs[src], ko, vo, d_n, shift, dbits, ws.hist, ws.hist_stride, ws.dtot);
         src ^= 1;
     }
     return hipGetLastError();
