@@ -301,7 +301,7 @@ def main():
                     help="skip timing the sigmoid and LogSumExp windows")
     ap.add_argument("--no-prune-stats", action="store_true",
                     help="skip timing the forward that keeps the pruning statistics")
-    ap.add_argument("--serve-rates", default="200,500,1000,2000,3000,4000,6000",
+    ap.add_argument("--serve-rates", default="200,500,1000,2000,3000,4000,6000,8000",
                     help="req/s; the quoted 200-2000 and rates up to past saturation")
     ap.add_argument("--serve-seconds", type=float, default=11.0,
                     help="load duration per rate, the first --serve-warmup s not measured")
