@@ -194,7 +194,10 @@ def _one_tile_soup(seed, n, mode):
     """n small triangles whose tight boxes all fall in tile (1, 1) of a 64x64
     image, every triangle flat at depth z (so its depth key is exactly z).
     mode: 'equal' (one key), 'ulps' (keys 3.0 + 0..199 ulps: only the low
-    byte differs), 'spread' (z in [2, 4) with repeats), 'wide' (z in [0.5, 40))."""
+    byte differs), 'spread' (z in [2, 4) with repeats), 'wide' (z in [0.5, 40)),
+    'clustered' ('ulps' with 2% of the triangles at z = 30: a wide key range
+    whose entries nearly all share their leading bits), 'few' (five depths in
+    [2, 25): long runs of equal keys over a wide range)."""
     rng = np.random.default_rng(seed)
     W = H = 64
     cam = synth.identity_camera(W, H)
@@ -207,6 +210,11 @@ def _one_tile_soup(seed, n, mode):
         z = rng.uniform(2.0, 4.0, n).astype(np.float32)
         rep = rng.random(n) < 0.2
         z[rep] = z[rng.integers(0, n, int(rep.sum()))]
+    elif mode == "clustered":
+        z = (np.float32(3.0).view(np.uint32) + rng.integers(0, 200, n).astype(np.uint32)).view(np.float32)
+        z[rng.random(n) < 0.02] = np.float32(30.0)
+    elif mode == "few":
+        z = rng.choice(rng.uniform(2.0, 25.0, 5), n).astype(np.float32)
     else:
         z = rng.uniform(0.5, 40.0, n).astype(np.float32)
     ctr = rng.uniform(21.0, 26.0, (n, 2))
@@ -224,12 +232,15 @@ def _one_tile_soup(seed, n, mode):
                                     (1024, "ulps"), (1025, "ulps"), (1500, "equal"),
                                     (2048, "spread"), (2049, "spread"), (4096, "spread"),
                                     (4097, "ulps"), (5000, "equal"), (5000, "ulps"),
-                                    (5000, "spread"), (4500, "wide")])
+                                    (5000, "spread"), (4500, "wide"), (300, "clustered"),
+                                    (1024, "clustered"), (3000, "clustered"), (900, "few"),
+                                    (2500, "few")])
 def test_bins_one_deep_tile(n, mode):
     """The per-tile depth sort in its three forms (one wave up to 1024
     entries, four waves and a merge up to 4096, global ping-pong beyond) and
-    with 0, 1, 3 and 4 digit passes; ties keep index order.  Bit-exact
-    against the oracle's stable sort."""
+    with 0, 1, 3 and 4 digit passes, over key sets with long runs of equal
+    keys or of keys equal in all but the low byte ('clustered', 'few'); ties
+    keep index order.  Bit-exact against the oracle's stable sort."""
     sc, cam = _one_tile_soup(61, n, mode)
     cfg = Config(sh_degree=0)
     ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
