@@ -74,20 +74,23 @@ union RecView {
 //
 // The staged copy holds C_k relative to the tile's corner pixel (tx0, ty0)
 // instead of the record's anchor, so a lane evaluates u_k = A_k dx + B_k dy +
-// C_k with its own fixed offset in the tile (no per-step conversion).
-template <class Stage>
+// C_k with its own fixed offset in the tile (no per-step conversion).  The
+// forward (ZA) needs no anchor after that: it stages the depth in the
+// anchor's four bytes, so a step reads C[2], z and o with one 16-byte load.
+template <bool ZA, class Stage>
 __device__ __forceinline__ void write_stage(Stage& S, RecView& u, int tx0, int ty0)
 {
     const double ox = (double)(tx0 - u.r.ax), oy = (double)(ty0 - u.r.ay);
 #pragma unroll
     for (int k = 0; k < 3; ++k) u.r.C[k] = fma(u.r.A[k], ox, fma(u.r.B[k], oy, u.r.C[k]));
+    if constexpr (ZA) u.q[4].z = u.r.z;   // bytes 72-75: the anchor
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) S.q[c][threadIdx.x] = u.q[c];
-    S.z[threadIdx.x] = u.r.z;
+    if constexpr (!ZA) S.z[threadIdx.x] = u.r.z;
     if constexpr (Stage::kLse) S.ps[threadIdx.x] = u.r.phis;
 }
 
-template <class Stage>
+template <bool ZA = false, class Stage>
 __device__ __forceinline__ void stage_copy(Stage& S, const TriRecord* __restrict__ rec,
                                            uint32_t tri, int tx0, int ty0)
 {
@@ -96,10 +99,10 @@ __device__ __forceinline__ void stage_copy(Stage& S, const TriRecord* __restrict
     constexpr int nc = Stage::kLse ? 8 : 7;   // phis sits in chunk 7
 #pragma unroll
     for (int c = 0; c < nc; ++c) u.q[c] = src[c];
-    write_stage(S, u, tx0, ty0);
+    write_stage<ZA>(S, u, tx0, ty0);
 }
 
-template <class Stage>
+template <bool ZA = false, class Stage>
 __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restrict__ rec,
                                               uint32_t tri, int tx0, int ty0)
 {
@@ -107,7 +110,7 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
     RecView u;
 #pragma unroll
     for (int c = 0; c < 8; ++c) u.q[c] = src[c];
-    write_stage(S, u, tx0, ty0);
+    write_stage<ZA>(S, u, tx0, ty0);
     uint32_t cx = 0, cy = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -155,13 +158,13 @@ __device__ __forceinline__ uint32_t stage_rec(Stage& S, const TriRecord* __restr
     return m;
 }
 
-template <class Stage>
+template <bool ZA = false, class Stage>
 __device__ __forceinline__ TriRecord read_rec(const Stage& S, int j)
 {
     RecView u;
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) u.q[c] = S.q[c][j];
-    u.r.z = S.z[j];
+    u.r.z = ZA ? u.q[4].z : S.z[j];
     if constexpr (Stage::kLse) u.r.phis = S.ps[j];
     return u.r;
 }
@@ -240,12 +243,13 @@ __device__ __forceinline__ bool frag_alpha(const TriRecord& r, double dx, double
         return true;
     } else if constexpr (WIN == TS_WINDOW_LSE) {
         const double u = lse_u(r.A, r.B, r.C, dx, dy, (double)r.phis, f);
-        window_alpha(u > 0.0 ? u : 0.0, r.o, r.sigma, alpha_max, f);
+        window_alpha((float)(u > 0.0 ? u : 0.0), r.o, r.sigma, alpha_max, f);
         return u > 0.0;
     } else {
         const double u = K ? edge_min(r.A, r.B, r.C, dx, dy, k)
                            : edge_min_value(r.A, r.B, r.C, dx, dy);
-        window_alpha(fmax(u, 0.0), r.o, r.sigma, alpha_max, f);
+        // clamped after the conversion: one FP32 max instead of two FP64 ones
+        window_alpha(fmaxf((float)u, 0.f), r.o, r.sigma, alpha_max, f);
         f.k = k;
         return u > 0.0;
     }
@@ -347,7 +351,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         if (tid < n) {
             const uint32_t tri = vals[b + tid];
             S.tri[tid] = ST ? 0u : tri;   // the statistics' max-weight word
-            S.hit[tid] = (uint16_t)stage_rec(S, rec, tri, J.tx * kTile, J.ty * kTile);
+            S.hit[tid] = (uint16_t)stage_rec<true>(S, rec, tri, J.tx * kTile, J.ty * kTile);
         }
         if (tid < kBatch / 2) S.comp[tid] = 0u;
         __syncthreads();
@@ -371,7 +375,7 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             const int jl = jn;              // this step's entry of the row's list
             const int j = act ? jl : 0;
             jn = lst[k + 1 < kBatch ? k + 1 : 0];
-            const TriRecord r = read_rec(S, j);
+            const TriRecord r = read_rec<true>(S, j);
             Frag f;
             const bool in = frag_alpha<WIN, false>(r, dxt, dyt, cfg.alpha_max, f);
             const bool contrib = act && in && f.a >= cfg.alpha_min;

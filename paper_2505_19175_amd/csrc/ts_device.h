@@ -166,10 +166,10 @@ __device__ __forceinline__ double edge_min(const double* A, const double* B, con
     return u;
 }
 
-__device__ __forceinline__ void window_alpha(double u64, float o, float sigma, float alpha_max,
+__device__ __forceinline__ void window_alpha(float u, float o, float sigma, float alpha_max,
                                              Frag& f)
 {
-    f.u = (float)u64;
+    f.u = u;
     f.lg = __builtin_amdgcn_logf(f.u);            // v_log_f32: log2
     f.I = __builtin_amdgcn_exp2f(sigma * f.lg);   // v_exp_f32: 2^x
     f.oI = o * f.I;
