@@ -367,9 +367,10 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         const int len = per_row(P.g, L.n0, L.n1, L.n2, L.n3);
         const uint8_t* lst = S.list[4 * P.w + P.g];
         int jn = lst[0];                 // next entry (read one step ahead)
-        for (int k = 0;; ++k) {
-            const bool act = !done && k < len;
-            if (__ballot(act) == 0ull) break;
+        bool act = !done && 0 < len;
+        // the test at the bottom keeps the loop a single block (no copies
+        // of the blend state per step)
+        if (__ballot(act) != 0ull) for (int k = 0;;) {
             // an idle lane reads slot 0 (always staged): a stale slot could hold
             // non-finite values, and 0 * inf in the branch-free blend is NaN
             const int jl = jn;              // this step's entry of the row's list
@@ -415,6 +416,9 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
                     }
                 }
             }
+            ++k;
+            act = !done && k < len;
+            if (__ballot(act) == 0ull) break;
         }
         const bool all_done = __syncthreads_and(done);
         if (J.blocks && tid < n) J.blocks[b + tid] = (uint16_t)(S.comp[tid >> 1] >> (16 * (tid & 1)));
