@@ -302,22 +302,25 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
     if (threadIdx.x == 0) dtot[blockIdx.x] = running;
 }
 
-// Stable scatter.  Keys of a block are read striped (key r*256 + tid), so the
-// stable order inside the block is (round, wave, lane).  Each wave finds the
-// lanes sharing its digit with dbits ballots; per (round, wave, digit) counts
-// in LDS are scanned per digit to give every key its rank.  The block's keys
-// are first placed in LDS in their sorted order, then written out by
-// consecutive lanes, so a store instruction covers a few runs of consecutive
-// addresses instead of up to 64 scattered words.
+// Stable scatter.  Wave w of a block reads keys w * 512 + r * 64 + lane of the
+// block's 2048 (round r), so the stable order inside the block is (wave,
+// round, lane).  In each round the lanes sharing a digit are found with dbits
+// ballots; the group's leader adds the group size to its wave's count of the
+// digit and gets back the count before it (the wave's earlier rounds: a
+// wave's LDS operations take effect in program order).  The block's keys are
+// then placed in LDS in their sorted order and written out by consecutive
+// lanes, so a store instruction covers a few runs of consecutive addresses
+// instead of up to 64 scattered words.
 __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ d_n,
     int shift, int dbits, const uint32_t* __restrict__ hist, int64_t stride,
     const uint32_t* __restrict__ dtot)
 {
+    constexpr int kWaveKeys = kChunk / (kBlock / 64);   // 512 keys per wave
     __shared__ uint32_t s_off[kRadix];   // output position of the block's k-th key of digit d: s_off[d] + k
     __shared__ uint32_t s_lst[kRadix];   // first LDS slot of digit d
-    __shared__ uint16_t s_cnt[kItems * 4][kRadix];
+    __shared__ uint32_t s_cnt[kBlock / 64][kRadix];   // per wave and digit: count, then the waves before
     __shared__ uint32_t s_key[kChunk];
     __shared__ uint32_t s_val[kChunk];
     __shared__ uint32_t s_tmp[4];
@@ -333,14 +336,14 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t dpre = block_exclusive_scan(dig ? dtot[tid] : 0u, tot, s_tmp);
     const uint32_t gbase = dig ? dpre + hist[tid * stride + b] : 0u;
 #pragma unroll
-    for (int s = 0; s < kItems * 4; ++s) s_cnt[s][tid] = 0;
+    for (int q = 0; q < kBlock / 64; ++q) s_cnt[q][tid] = 0u;
     __syncthreads();
 
-    uint32_t key[kItems], val[kItems], rank[kItems];
+    uint32_t key[kItems], val[kItems], within[kItems];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int j = r * kBlock + tid;
+        const int j = w * kWaveKeys + r * 64 + lane;
         const bool ok = j < nloc;
         key[r] = ok ? kin[b * kChunk + j] : 0u;
         val[r] = ok ? vin[b * kChunk + j] : 0u;
@@ -354,15 +357,19 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
                 m &= set ? bal : ~bal;
             }
         }
-        rank[r] = (uint32_t)__popcll(m & lt);
-        if (ok && (m & lt) == 0ull) s_cnt[r * 4 + w][d] = (uint16_t)__popcll(m);
+        const uint32_t rank = (uint32_t)__popcll(m & lt);
+        const uint32_t lead = m != 0ull ? (uint32_t)__builtin_ctzll(m) : (uint32_t)lane;
+        uint32_t before = 0u;
+        if (ok && rank == 0u) before = atomicAdd(&s_cnt[w][d], (uint32_t)__popcll(m));
+        within[r] = (uint32_t)__shfl((int)before, (int)lead, 64) + rank;
     }
     __syncthreads();
+    // per digit: the counts of the waves before each wave, and the block's count
     uint32_t run = 0;
 #pragma unroll
-    for (int s = 0; s < kItems * 4; ++s) {
-        const uint32_t c = s_cnt[s][tid];
-        s_cnt[s][tid] = (uint16_t)run;
+    for (int q = 0; q < kBlock / 64; ++q) {
+        const uint32_t c = s_cnt[q][tid];
+        s_cnt[q][tid] = run;
         run += c;
     }
     uint32_t btot;
@@ -372,9 +379,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        if (r * kBlock + tid < nloc) {
+        if (w * kWaveKeys + r * 64 + lane < nloc) {
             const uint32_t d = (key[r] >> shift) & mask;
-            const uint32_t q = s_lst[d] + s_cnt[r * 4 + w][d] + rank[r];
+            const uint32_t q = s_lst[d] + s_cnt[w][d] + within[r];
             s_key[q] = key[r];
             s_val[q] = val[r];
         }
