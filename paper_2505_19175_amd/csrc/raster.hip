@@ -350,10 +350,12 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
         __syncthreads();
         if (tid < n) {
             const uint32_t tri = vals[b + tid];
-            S.tri[tid] = ST ? 0u : tri;   // the statistics' max-weight word
+            // the statistics' max-weight word; without statistics, the blocks
+            // where the entry composited (one word per entry: no shifts per step)
+            S.tri[tid] = 0u;
             S.hit[tid] = (uint16_t)stage_rec<true>(S, rec, tri, J.tx * kTile, J.ty * kTile);
         }
-        if (tid < kBatch / 2) S.comp[tid] = 0u;
+        if (ST && tid < kBatch / 2) S.comp[tid] = 0u;
         __syncthreads();
         const Lens L = build_lists(S, n, P.w, lane, n, n, n, n);
         uint32_t* px = reinterpret_cast<uint32_t*>(S.hit);   // 16 bits per entry
@@ -406,8 +408,10 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             if (ST || J.blocks) {
                 const uint64_t cm = __ballot(comp);
                 const uint32_t rowbits = (uint32_t)(cm >> (16 * P.g)) & 0xffffu;
-                if (J.blocks && P.i == 0 && rowbits != 0u)   // the entry composited in this block
-                    atomicOr(&S.comp[jl >> 1], my_bit << (16 * (jl & 1)));
+                if (J.blocks && P.i == 0 && rowbits != 0u) {   // the entry composited in this block
+                    if constexpr (ST) atomicOr(&S.comp[jl >> 1], my_bit << (16 * (jl & 1)));
+                    else atomicOr(&S.tri[jl], my_bit);
+                }
                 if constexpr (ST) {   // pruning statistics of the row's entry, in LDS
                     const float mw = row_max_f(tw);
                     if (P.i == 0 && rowbits != 0u) {
@@ -421,7 +425,9 @@ __device__ __forceinline__ void fwd_tile(const TriRecord* __restrict__ rec,
             if (__ballot(act) == 0ull) break;
         }
         const bool all_done = __syncthreads_and(done);
-        if (J.blocks && tid < n) J.blocks[b + tid] = (uint16_t)(S.comp[tid >> 1] >> (16 * (tid & 1)));
+        if (J.blocks && tid < n)
+            J.blocks[b + tid] = ST ? (uint16_t)(S.comp[tid >> 1] >> (16 * (tid & 1)))
+                                   : (uint16_t)S.tri[tid];
         if constexpr (ST) {
             if (tid < n && S.tri[tid] != 0u) {
                 const uint32_t tri = vals[b + tid];
@@ -495,10 +501,10 @@ __global__ __launch_bounds__(256) void k_raster_fwd_queue(
     float* __restrict__ out_depth)
 {
     __shared__ StageT<WIN> S;
-    // the queue slot lives in the stage's forward block-mask words: every
-    // thread reads it before fwd_tile's first barrier, and fwd_tile clears
-    // those words only after that barrier.  A separate variable would push
-    // the workgroup past 25 LDS allocation units (four per CU, not five).
+    // the queue slot lives in the stage's block-mask words of the forward
+    // with statistics, which this forward never touches.  A separate
+    // variable would push the workgroup past 25 LDS allocation units (four
+    // per CU, not five).
     uint32_t& s_t = S.comp[0];
     const uint32_t nviews = ctl[0], total = ctl[1];
     for (;;) {
