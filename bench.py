@@ -40,14 +40,14 @@ TRAFFIC = {
     "project_bwd": {"files": ["paper_2505_19175_amd/csrc/backproject.hip",
                               "paper_2505_19175_amd/csrc/geometry.h",
                               "paper_2505_19175_amd/csrc/ts_device.h"],
-                    "src": "4150617e0df1ca4364cfeae2464888567b3d2f517b055d006a18358688d30325",
+                    "src": "2f75c1b29f27ca26ded13886dbdef84017ac581d79288b4e0be0c2219d11aea2",
                     "fetch_kib": 1.615e5, "write_kib": 7.807e5,
                     "fetch_scale": 2.0, "write_scale": 1.0},
     "project": {"files": ["paper_2505_19175_amd/csrc/project.hip",
                           "paper_2505_19175_amd/csrc/geometry.h",
                           "paper_2505_19175_amd/csrc/ts_device.h"],
-                "src": "ad298663041bdf233606a97e034e3f4754496437959e0e84a3ba9abc8e133f22",
-                "fetch_kib": 2.148e5, "write_kib": 3.102e5,
+                "src": "ff00d4a2a94574088ef47d699290f7606ccaf8e6ec59cef61445af4cc2573524",
+                "fetch_kib": 2.148e5, "write_kib": 3.104e5,
                 "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
