@@ -250,6 +250,27 @@ def test_bins_one_deep_tile(n, mode):
     _check_bins(st, sc, cam, cfg)
 
 
+def test_bins_three_radix_passes():
+    """A 4160x4160 view (260 x 260 = 67600 tiles, more than 2^16): the sort by
+    tile id takes three passes of six bits instead of two; bins bit-exact
+    against the oracle's stable sort."""
+    sc, cam = random_soup(65, 3000, W=4160, H=4160, size=0.004, deg=0)
+    # a third of the triangles moved down to the bottom rows of tiles (ids
+    # above 2^16), at the same depth (the oracle gets the same float32 values)
+    rng = np.random.default_rng(66)
+    v = sc.v.astype(np.float64)
+    z = v[2000:, :, 2].mean(1)
+    dy = rng.uniform(4040.0, 4150.0, 1000) - (v[2000:, :, 1].mean(1) * cam.fy / z + cam.cy)
+    v[2000:, :, 1] += (dy * z / cam.fy)[:, None]
+    sc.v[...] = v.astype(np.float32)
+    cfg = Config(sh_degree=0)
+    assert ((cam.width + 15) // 16) * ((cam.height + 15) // 16) > 1 << 16
+    ras, st, sct, out = G.gpu_forward(sc, cam, cfg)
+    M = _check_bins(st, sc, cam, cfg)
+    assert M > 2000
+    assert int(st.keys.cpu().numpy()[:M].view(np.uint64).max() >> np.uint64(32)) >= 1 << 16
+
+
 @pytest.mark.parametrize("n,mode", [(4097, "ulps"), (5000, "equal"), (20000, "spread"),
                                     (20000, "ulps"), (45000, "wide")])
 def test_bins_segmented_sort(n, mode):
