@@ -1091,13 +1091,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_scan(const uint32_t* __restrict_
     }
 }
 
-// What the segmented scatter keeps in LDS: the chunk's rank tables and digit
-// bases only (17 KB, so eight waves per SIMD fit).
-struct RankSmem {
-    uint16_t cnt[kItems * 4][kRadix];
-    uint32_t base[kRadix];
-};
-
+// Stable scatter of one chunk of a huge tile, ranked and written as in
+// k_radix_scatter: wave w ranks the chunk's entries w * 512 + r * 64 + lane
+// (the leader of a group takes the count of its digit in the wave's earlier
+// rounds from the return value of its LDS add), the chunk is placed in LDS in
+// sorted order and written out by consecutive lanes.  Positions start at the
+// chunk's offsets from the scanned (digit, chunk) histogram of its tile.
 __global__ __launch_bounds__(kBlock) void k_seg_scatter(
     const uint32_t* __restrict__ hl, const uint32_t* __restrict__ cst, int num_tiles,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ kin,
@@ -1105,24 +1104,81 @@ __global__ __launch_bounds__(kBlock) void k_seg_scatter(
     const uint32_t* __restrict__ hist, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, uint64_t* __restrict__ keys)
 {
-    __shared__ RankSmem sm;
+    constexpr int kWaveKeys = kChunk / (kBlock / 64);   // 512 entries per wave
+    __shared__ uint32_t s_off[kRadix];   // output position of the chunk's k-th entry of digit d: s_off[d] + k
+    __shared__ uint32_t s_lst[kRadix];   // first LDS slot of digit d
+    __shared__ uint32_t s_cnt[kBlock / 64][kRadix];   // per wave and digit: count, then the waves before
+    __shared__ uint32_t s_key[kChunk];
+    __shared__ uint32_t s_val[kChunk];
+    __shared__ uint32_t s_tmp[4];
     SegChunk q;
     if (!seg_chunk(blockIdx.x, hl, cst, num_tiles, ranges, q)) return;
-    const int w = threadIdx.x >> 6;
-    uint32_t key[kItems], val[kItems], rank[kItems];
-    seg_load(q, kin, vin, depth, key, val);
-    rank_chunk(key, (int)q.n, shift, sm, rank);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nloc = (int)q.n;
+#pragma unroll
+    for (int c = 0; c < kBlock / 64; ++c) s_cnt[c][tid] = 0u;
+    __syncthreads();
+
+    uint32_t key[kItems], val[kItems], within[kItems];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int j = w * kWaveKeys + r * 64 + lane;
+        const bool ok = j < nloc;
+        key[r] = 0u;
+        val[r] = 0u;
+        if (ok) {
+            const uint32_t pos = q.s0 + q.lo + (uint32_t)j;
+            val[r] = vin[pos];
+            key[r] = kin ? kin[pos] : __float_as_uint(depth[val[r]]);
+        }
+        const uint32_t d = (key[r] >> shift) & 0xffu;
+        uint64_t m = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t bal = __ballot(set);
+            m &= set ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & lt);
+        const uint32_t lead = m != 0ull ? (uint32_t)__builtin_ctzll(m) : (uint32_t)lane;
+        uint32_t before = 0u;
+        if (ok && rank == 0u) before = atomicAdd(&s_cnt[w][d], (uint32_t)__popcll(m));
+        within[r] = (uint32_t)__shfl((int)before, (int)lead, 64) + rank;
+    }
+    __syncthreads();
+    uint32_t run = 0;
+#pragma unroll
+    for (int c = 0; c < kBlock / 64; ++c) {
+        const uint32_t x = s_cnt[c][tid];
+        s_cnt[c][tid] = run;
+        run += x;
+    }
+    uint32_t btot;
+    const uint32_t lstart = block_exclusive_scan(run, btot, s_tmp);   // barriers inside
+    s_lst[tid] = lstart;
     // the chunk's first position for each digit, from the scanned histogram
-    sm.base[threadIdx.x] = hist[(int64_t)blockIdx.x * kRadix + threadIdx.x];
+    s_off[tid] = hist[(int64_t)blockIdx.x * kRadix + tid] - lstart;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        if ((uint32_t)(r * kBlock + threadIdx.x) < q.n) {
+        if (w * kWaveKeys + r * 64 + lane < nloc) {
             const uint32_t d = (key[r] >> shift) & 0xffu;
-            const uint32_t pos = sm.base[d] + sm.cnt[r * 4 + w][d] + rank[r];
-            if (kout) kout[pos] = key[r];
-            vout[pos] = val[r];
-            if (keys) keys[pos] = tile_key(q.t, key[r]);
+            const uint32_t slot = s_lst[d] + s_cnt[w][d] + within[r];
+            s_key[slot] = key[r];
+            s_val[slot] = val[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int j = r * kBlock + tid;
+        if (j < nloc) {
+            const uint32_t k = s_key[j];
+            const uint32_t pos = s_off[(k >> shift) & 0xffu] + (uint32_t)j;
+            if (kout) kout[pos] = k;
+            vout[pos] = s_val[j];
+            if (keys) keys[pos] = tile_key(q.t, k);
         }
     }
 }
