@@ -1018,26 +1018,10 @@ __device__ __forceinline__ bool seg_chunk(uint32_t c, const uint32_t* __restrict
     return true;
 }
 
-// Pass input: pass 0 reads the tile's entries from vals and their keys from
-// depth; later passes read the previous pass's (key, value) buffers.
-__device__ __forceinline__ void seg_load(const SegChunk& q, const uint32_t* __restrict__ kin,
-                                         const uint32_t* __restrict__ vin,
-                                         const float* __restrict__ depth,
-                                         uint32_t (&key)[kItems], uint32_t (&val)[kItems])
-{
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const uint32_t j = (uint32_t)(r * kBlock + threadIdx.x);
-        key[r] = 0u;
-        val[r] = 0u;
-        if (j < q.n) {
-            const uint32_t pos = q.s0 + q.lo + j;
-            val[r] = vin[pos];
-            key[r] = kin ? kin[pos] : __float_as_uint(depth[val[r]]);
-        }
-    }
-}
-
+// Per-chunk digit histogram.  The first pass (kin null) gathers the keys from
+// depth and, when kfirst is set, keeps them there at the entries' positions,
+// so its scatter reads them in order instead of gathering them again; later
+// passes read only the keys.
 __global__ __launch_bounds__(kBlock) void k_seg_hist(const uint32_t* __restrict__ hl,
                                                      const uint32_t* __restrict__ cst,
                                                      int num_tiles,
@@ -1045,18 +1029,29 @@ __global__ __launch_bounds__(kBlock) void k_seg_hist(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ kin,
                                                      const uint32_t* __restrict__ vin,
                                                      const float* __restrict__ depth, int shift,
-                                                     uint32_t* __restrict__ hist)
+                                                     uint32_t* __restrict__ hist,
+                                                     uint32_t* __restrict__ kfirst)
 {
     __shared__ uint32_t h[kRadix];
     SegChunk q;
     if (!seg_chunk(blockIdx.x, hl, cst, num_tiles, ranges, q)) return;
     h[threadIdx.x] = 0u;
     __syncthreads();
-    uint32_t key[kItems], val[kItems];
-    seg_load(q, kin, vin, depth, key, val);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r)
-        if ((uint32_t)(r * kBlock + threadIdx.x) < q.n) atomicAdd(&h[(key[r] >> shift) & 0xffu], 1u);
+    for (int r = 0; r < kItems; ++r) {
+        const uint32_t j = (uint32_t)(r * kBlock + threadIdx.x);
+        if (j < q.n) {
+            const uint32_t pos = q.s0 + q.lo + j;
+            uint32_t key;
+            if (kin) {
+                key = kin[pos];
+            } else {
+                key = __float_as_uint(depth[vin[pos]]);
+                if (kfirst) kfirst[pos] = key;
+            }
+            atomicAdd(&h[(key >> shift) & 0xffu], 1u);
+        }
+    }
     __syncthreads();
     hist[(int64_t)blockIdx.x * kRadix + threadIdx.x] = h[threadIdx.x];   // chunk-major
 }
@@ -1286,9 +1281,13 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
             const bool last = p == 3;
             uint32_t* kout = last ? nullptr : ws.tk[(p + 1) & 1];
             uint32_t* vout = last ? out.vals : ws.tv[(p + 1) & 1];
+            // the first pass keeps the gathered keys in tk[0], free until the
+            // second pass writes it
             hipLaunchKernelGGL(k_seg_hist, dim3(nc), dim3(kBlock), 0, stream,
                                (const uint32_t*)ws.hl, (const uint32_t*)ws.cst, num_tiles,
-                               out.ranges, kin, vin, depth, 8 * p, ws.hist);
+                               out.ranges, kin, vin, depth, 8 * p, ws.hist,
+                               p == 0 ? ws.tk[0] : nullptr);
+            if (p == 0) kin = ws.tk[0];
             hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)num_tiles), dim3(kBlock), 0, stream,
                                (const uint32_t*)ws.hl, (const uint32_t*)ws.cst, num_tiles,
                                out.ranges, ws.hist);
