@@ -19,7 +19,9 @@
 //
 // Every global pass is reduce-then-scan: per-block digit histograms, a scan
 // of the histogram matrix, and a stable scatter whose in-block ranks come from
-// wavefront ballots.  No kernel waits on another block, so nothing can spin.
+// wavefront ballots and the group leaders' returned LDS counts, staged in LDS
+// so the block writes runs of consecutive addresses.  No kernel waits on
+// another block, so nothing can spin.
 // Element counts are read from device memory, so the whole chain can run
 // without a host round trip (grids sized by upper bounds).
 #include "ts_device.h"
