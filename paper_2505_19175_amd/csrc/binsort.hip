@@ -683,14 +683,9 @@ __device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float*
 
 // ---- one wave per tile (L <= kWaveMax) ------------------------------------
 
-struct WaveSmem {   // a sorted quarter of a long tile, for the merge
-    uint32_t key[kWaveMax];
-    uint32_t val[kWaveMax];
-};
-
 union TileSortSmem {
     SortSmem blk;
-    WaveSmem wave[kBlock / 64];
+    uint64_t kv[(kBlock / 64) * kWaveMax];   // a long tile's four sorted quarters, merged in place
 };
 
 
@@ -768,94 +763,108 @@ __device__ __forceinline__ void bitonic_stages(uint64_t (&x)[K], int lane)
     }
 }
 
+// Loads the L <= 64 K entries vals[b ..] as keys (pads: the largest key) and
+// sorts them with the wave's register network.
 template <int K>
-__device__ void bitonic_tile(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
-                             uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
-                             WaveSmem& sm, bool to_lds)
+__device__ __forceinline__ void wave_sorted(int L, uint32_t b, const float* __restrict__ depth,
+                                            const uint32_t* __restrict__ vals, uint64_t (&x)[K])
 {
     const int lane = threadIdx.x & 63;
-    uint64_t x[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const int e = lane * K + r;
         x[r] = ~0ull;
         if (e < L) {
-            const uint32_t v = vals[s0 + e];
+            const uint32_t v = vals[b + e];
             x[r] = ((uint64_t)__float_as_uint(depth[v]) << 32) | v;
         }
     }
     bitonic_stages<K, 2, 1>(x, lane);
+}
+
+template <int K>
+__device__ void bitonic_tile(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
+                             uint32_t* __restrict__ vals, uint64_t* __restrict__ keys)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t x[K];
+    wave_sorted<K>(L, s0, depth, vals, x);
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         const int e = lane * K + r;
         if (e < L) {
-            const uint32_t v = (uint32_t)x[r], k = (uint32_t)(x[r] >> 32);
-            if (to_lds) {
-                sm.key[e] = k;
-                sm.val[e] = v;
-            } else {
-                vals[s0 + e] = v;
-                if (keys) keys[s0 + e] = tile_key(t, k);
-            }
+            vals[s0 + e] = (uint32_t)x[r];
+            if (keys) keys[s0 + e] = tile_key(t, (uint32_t)(x[r] >> 32));
         }
     }
 }
 
 // The wave-level sort: the smallest network that holds the tile.
 __device__ void sort_tile_bitonic(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
-                                  uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
-                                  WaveSmem& sm, bool to_lds)
+                                  uint32_t* __restrict__ vals, uint64_t* __restrict__ keys)
 {
-    if (L <= 64) bitonic_tile<1>(L, s0, t, depth, vals, keys, sm, to_lds);
-    else if (L <= 128) bitonic_tile<2>(L, s0, t, depth, vals, keys, sm, to_lds);
-    else if (L <= 256) bitonic_tile<4>(L, s0, t, depth, vals, keys, sm, to_lds);
-    else if (L <= 512) bitonic_tile<8>(L, s0, t, depth, vals, keys, sm, to_lds);
-    else bitonic_tile<16>(L, s0, t, depth, vals, keys, sm, to_lds);
+    if (L <= 64) bitonic_tile<1>(L, s0, t, depth, vals, keys);
+    else if (L <= 128) bitonic_tile<2>(L, s0, t, depth, vals, keys);
+    else if (L <= 256) bitonic_tile<4>(L, s0, t, depth, vals, keys);
+    else if (L <= 512) bitonic_tile<8>(L, s0, t, depth, vals, keys);
+    else bitonic_tile<16>(L, s0, t, depth, vals, keys);
 }
 
-// First index of sorted a[0, n) whose key is above x (upper = true) or at
-// least x (upper = false).
-__device__ __forceinline__ int bound(const uint32_t* a, int n, uint32_t x, bool upper)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const uint32_t v = a[mid];
-        if (upper ? v <= x : v < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Stable 4-way merge of a run of L entries whose four quarters (contiguous
-// index ranges of length Q, the last one shorter) each wave has sorted into
-// its LDS buffer: every entry goes to its own rank plus, per other quarter,
-// the number of that quarter's entries preceding it -- keys below, and equal
-// keys of earlier quarters -- found by binary search.  The result is the
-// (depth, index) order.
-__device__ void merge_quarters(int L, int Q, uint32_t s0, uint32_t t,
+// A long tile: wave w sorts quarter w (entries w * Qa .. of the tile, Qa =
+// ceil(L / 4)) with the register network into kv[w * 64 K ..], every one of
+// its 64 K slots written (past the quarter, the largest key); then the
+// workgroup merges the four ascending runs in LDS with the last two levels of
+// the same direction-free network, and writes the first L keys out.
+template <int K>
+__device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
-                               const WaveSmem (&wv)[kBlock / 64])
+                               uint64_t* __restrict__ kv)
 {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    auto qlen = [&](int q) { return max(0, min(Q, L - q * Q)); };
-    const int mine = qlen(w);
-    for (int j = lane; j < mine; j += 64) {
-        const uint32_t k = wv[w].key[j];
-        int pos = j;
+    constexpr int Q = 64 * K, N = 4 * Q;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int Qa = (L + 3) >> 2;
+    const int q0 = w * Qa;
+    uint64_t x[K];
+    wave_sorted<K>(max(0, min(Qa, L - q0)), s0 + (uint32_t)q0, depth, vals, x);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q != w) pos += bound(wv[q].key, qlen(q), k, q < w);
-        vals[s0 + pos] = wv[w].val[j];
-        if (keys) keys[s0 + pos] = tile_key(t, k);
+    for (int r = 0; r < K; ++r) kv[w * Q + lane * K + r] = x[r];
+    __syncthreads();
+    for (int size = 2 * Q; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const bool flip = stride == (size >> 1);
+            for (int p = tid; p < N / 2; p += kBlock) {
+                int i, j;
+                if (flip) {   // e with e ^ (size - 1): the lower half of each block
+                    const int off = p & (stride - 1), blk = p - off;   // stride = size / 2
+                    i = 2 * blk + off;
+                    j = 2 * blk + size - 1 - off;
+                } else {
+                    const int off = p & (stride - 1);
+                    i = 2 * (p - off) + off;
+                    j = i + stride;
+                }
+                const uint64_t a = kv[i], b = kv[j];
+                if (b < a) {
+                    kv[i] = b;
+                    kv[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < L; e += kBlock) {
+        const uint64_t y = kv[e];
+        vals[s0 + e] = (uint32_t)y;
+        if (keys) keys[s0 + e] = tile_key(t, (uint32_t)(y >> 32));
     }
 }
 
 // Tiles taken in `order` (longest first); the first n_long of them are longer
 // than kWaveMax and get a whole workgroup each (four wave-level sorts of a
-// quarter each and a merge up to 4 kWaveMax entries, global ping-pong beyond);
-// every later workgroup gives each of its four waves one tile.  The instances of a tile arrive in index order; they
-// leave in (depth, index) order, with their 64-bit keys when keys is set.
+// quarter each and a merge in LDS up to 4 kWaveMax entries, global ping-pong
+// or the segmented sort beyond); every later workgroup gives each of its four
+// waves one tile.  The instances of a tile arrive in index order; they leave
+// in (depth, index) order, with their 64-bit keys when keys is set.
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ n_long,
@@ -883,25 +892,21 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     if (t >= (uint32_t)num_tiles) return;
     const uint32_t s0 = ranges[2 * t];
     const int64_t L = (int64_t)ranges[2 * t + 1] - (int64_t)s0;
-    const int w = threadIdx.x >> 6;
     if (blockIdx.x < nl && L > kHugeLen) {   // the whole workgroup, in global memory
         if (!segmented) sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
         return;   // else the segmented sort below takes the tile
     }
-    // one wave-level sort per wave: a whole tile, or a quarter of a long one
-    const bool split = blockIdx.x < nl;          // the same for the whole workgroup
-    const int Q = (int)((L + 3) >> 2);
-    const int wl = split ? max(0, min(Q, (int)L - w * Q)) : (int)L;
-    const uint32_t ws0 = split ? s0 + (uint32_t)(w * Q) : s0;
-    if (!split && wl == 1) {
+    if (blockIdx.x < nl) {   // the whole workgroup: four quarters and a merge
+        if (L <= 4 * 512) sort_long_tile<8>((int)L, s0, t, depth, vals, keys, sm.kv);
+        else sort_long_tile<16>((int)L, s0, t, depth, vals, keys, sm.kv);
+        return;
+    }
+    // one wave-level sort per wave: a whole tile
+    if (L == 1) {
         if (keys && (threadIdx.x & 63) == 0)
             keys[s0] = tile_key(t, __float_as_uint(depth[vals[s0]]));
-    } else if (wl > 0 && wl <= kWaveMax) {
-        sort_tile_bitonic(wl, ws0, t, depth, vals, keys, sm.wave[w], split);
-    }
-    if (split) {
-        __syncthreads();   // every quarter sorted, and all reads of vals done
-        merge_quarters((int)L, Q, s0, t, vals, keys, sm.wave);
+    } else if (L > 1 && L <= kWaveMax) {
+        sort_tile_bitonic((int)L, s0, t, depth, vals, keys);
     }
 }
 
