@@ -180,16 +180,18 @@ int ts_project(const float* v, const float* o, const float* sigma, const float* 
  * Tile binning and depth ordering (Supp. "Tile assignment", "Depth
  * sorting"): each visible triangle emits one instance per 16x16 tile of its
  * tight box; instances are stably ordered by (tile, depth key, triangle
- * index) and ranges[t] gives tile t's run.  Device radix sorts, no host
- * round trip unless h_count is non-NULL.
+ * index) and ranges[t] gives tile t's run.  Device counting and radix
+ * sorts, no host round trip unless h_count is non-NULL.
  *   ws/ws_bytes  workspace of ts_bin_sort_workspace_bytes(N, capacity, tiles)
  *   h_count      optional host uint32_t[2]: receives (M, N_v); the call then
- *                synchronises `stream` and sizes later launches exactly.
+ *                synchronises `stream` (and may size later launches exactly).
  *                With h_count == NULL the launches are sized by N and
  *                capacity and read M from out->d_count on the device.
  * Returns TS_ECAPACITY when M > capacity and h_count is non-NULL (M is left
- * in h_count[0] and d_count[0]); with h_count == NULL an overflow sets
- * d_count[2] and the lists hold only the first `capacity` instances.
+ * in h_count[0] and d_count[0]; the ranges and order then describe valid,
+ * possibly empty, runs); with h_count == NULL an overflow sets d_count[2]
+ * and the lists hold `capacity` of the M instances (which ones depends on
+ * the grouping path), each tile's run in (depth, index) order.
  */
 int ts_bin_sort(const ts_proj* proj, int64_t N, const ts_camera* cam, void* ws, size_t ws_bytes,
                 const ts_bins* out, uint32_t* h_count, hipStream_t stream);

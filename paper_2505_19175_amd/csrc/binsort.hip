@@ -3,27 +3,39 @@
 // The ordering the renderer needs is: instances grouped by tile, and inside a
 // tile front to back by the depth key, ties by triangle index.  Sorting the
 // 64-bit (tile, depth) keys of all M instances would take 6 radix passes over
-// M.  Instead:
+// M.  Instead the instances are first grouped by tile, then each tile's run
+// is put in depth order.  Grouping, when the tile counters fit in LDS (up to
+// kGroupTiles tiles) and the huge tiles are not sorted segment-wise:
+//   1'. G groups of consecutive triangles count their instances per tile in
+//       LDS (a G x tiles matrix), a column scan gives each group its offset
+//       inside each tile, one workgroup scans the tile totals into the ranges
+//       and the longest-first tile order, and the groups place every instance
+//       at tile start + group offset + an LDS cursor (four launches, no pass
+//       over the instance list)
+// Otherwise (more tiles, or the segmented sort of huge tiles, which needs the
+// runs in index order):
 //   1. count the tiles of every triangle, in index order, and scan the counts
 //   2. emit one instance per (triangle, tile) in index order
 //   3. stable LSD radix sort of the instances by tile id,
 //      ceil(log2 tiles / 8) passes over M with the bits split evenly between
 //      them; inside a tile the triangles are still in index order
+// Then:
 //   4. each tile's entries are put in (depth key, index) order: up to 1024
 //      entries by one wave, a bitonic network over 64-bit (depth, index)
 //      keys held in registers; up to 4096 by four waves (a quarter each) and
-//      a merge; beyond, a stable radix sort by depth of the index-ordered
-//      run (one workgroup with global ping-pong buffers, or the segmented
-//      sort below), skipping the 8-bit digits equal over the whole tile
-// A stable sort by depth of a list in index order is the (depth, index)
-// order, so the result is exactly the (tile, depth, index) order.  Nothing is
-// gathered in a random order except the depth key of each instance.
+//      a merge in LDS; beyond, a stable radix sort by depth of the run in
+//      index order (one workgroup with global ping-pong buffers, which first
+//      sorts by index a run that step 1' left in group order, or the
+//      segmented sort below), skipping the 8-bit digits equal over the tile
+// The keys of the networks are unique, and a stable sort by depth of a list
+// in index order is the (depth, index) order, so either way the result is
+// exactly the (tile, depth, index) order.
 //
-// Every global pass is reduce-then-scan: per-block digit histograms, a scan
-// of the histogram matrix, and a stable scatter whose in-block ranks come from
-// wavefront ballots and the group leaders' returned LDS counts, staged in LDS
-// so the block writes runs of consecutive addresses.  No kernel waits on
-// another block, so nothing can spin.
+// Every global pass of steps 1-3 is reduce-then-scan: per-block digit
+// histograms, a scan of the histogram matrix, and a stable scatter whose
+// in-block ranks come from wavefront ballots and the group leaders' returned
+// LDS counts, staged in LDS so the block writes runs of consecutive
+// addresses.  No kernel waits on another block, so nothing can spin.
 // Element counts are read from device memory, so the whole chain can run
 // without a host round trip (grids sized by upper bounds).
 #include "ts_device.h"
@@ -453,22 +465,30 @@ constexpr int kOrderThreads = 1024;
 
 constexpr int kHugeLen = 4 * kWaveMax;   // longest list one workgroup sorts in LDS
 
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(
-    const uint32_t* __restrict__ ranges, int n_host, const uint32_t* __restrict__ d_n,
-    uint32_t* __restrict__ order, uint32_t* __restrict__ n_long, uint32_t* __restrict__ n_huge)
+// The order of tiles 0 .. n-1 by one workgroup of kOrderThreads; len_of(t)
+// gives a tile's list length.
+struct OrderSmem {
+    uint32_t h[kLenBuckets];
+    uint32_t w[kOrderThreads / 64];
+    uint32_t nlong, nhuge;
+};
+
+template <class Len>
+__device__ void order_tiles(int n, Len len_of, uint32_t* __restrict__ order,
+                            uint32_t* __restrict__ n_long, uint32_t* __restrict__ n_huge,
+                            OrderSmem& sm)
 {
-    __shared__ uint32_t h[kLenBuckets];
-    __shared__ uint32_t s_w[kOrderThreads / 64];
-    __shared__ uint32_t s_long, s_huge;
+    uint32_t* h = sm.h;
+    uint32_t* s_w = sm.w;
+    uint32_t& s_long = sm.nlong;
+    uint32_t& s_huge = sm.nhuge;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int n = d_n ? (int)min(*d_n, (uint32_t)n_host) : n_host;
     for (int b = tid; b < kLenBuckets; b += kOrderThreads) h[b] = 0u;
     if (tid == 0) {
         s_long = 0u;
         s_huge = 0u;
     }
     __syncthreads();
-    auto len_of = [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; };
     auto key = [&](int t) {
         return (kLenBuckets - 1) - (int)min(len_of(t), (uint32_t)(kLenBuckets - 1));
     };
@@ -499,6 +519,16 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(
     for (int t = tid; t < n; t += kOrderThreads) order[atomicAdd(&h[key(t)], 1u)] = (uint32_t)t;
 }
 
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(
+    const uint32_t* __restrict__ ranges, int n_host, const uint32_t* __restrict__ d_n,
+    uint32_t* __restrict__ order, uint32_t* __restrict__ n_long, uint32_t* __restrict__ n_huge)
+{
+    __shared__ OrderSmem sm;
+    const int n = d_n ? (int)min(*d_n, (uint32_t)n_host) : n_host;
+    order_tiles(
+        n, [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; }, order, n_long, n_huge, sm);
+}
+
 void launch_tile_order(const uint32_t* ranges, int num_tiles, const uint32_t* d_tiles,
                        uint32_t* order, hipStream_t stream, uint32_t* n_long, uint32_t* n_huge)
 {
@@ -518,6 +548,322 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tfi
     const uint32_t t = tfin[p];
     if (p == 0 || tfin[p - 1] != t) ranges[2 * t] = (uint32_t)p;
     if (p == m - 1 || tfin[p + 1] != t) ranges[2 * t + 1] = (uint32_t)(p + 1);
+}
+
+// ---------------------------------------------------------------------------
+// 1'. grouping by group tile counts (up to kGroupTiles tiles)
+// ---------------------------------------------------------------------------
+// When the tile counters fit in LDS, steps 1-3 become four launches with no
+// pass over the instance list: G groups of consecutive entries count their
+// instances per tile in LDS (G x tiles matrix), a column scan turns the matrix
+// into each group's offset inside each tile, one workgroup scans the tile
+// totals into the ranges and the longest-first order, and the groups walk
+// their entries again and place every instance at its tile's start + the
+// group's offset + an LDS cursor.  Inside a tile the instances are then in
+// group order but not in index order inside a group; the per-tile sort orders
+// by the unique (depth, index) key anyway (the workgroup sort of the huge
+// tiles sorts by index first).
+constexpr int kGroupThreads = 1024;
+constexpr int kMaxGroups = 256;
+constexpr int kGroupEntries = 4096;   // fewest entries per group
+constexpr int kGroupTiles = 12288;    // tile counters in LDS (48 KB)
+
+constexpr int kGroupRun = 8;   // consecutive entries a thread loads at once
+
+// The group a workgroup takes.  Workgroups are dealt to the eight XCDs in
+// turn, so consecutive groups go to one XCD: they write neighbouring slots of
+// every tile, and fewer cache lines are written in part by several XCDs'
+// caches.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_group(int G)
+{
+    const int b = blockIdx.x;
+    return (G % kXcds) == 0 ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
+}
+
+// Entries [e0, e1) of group g: ceil(n / G), rounded up to whole runs.
+__device__ __forceinline__ void group_span(int64_t n, int G, int g, int64_t& e0, int64_t& e1)
+{
+    int64_t per = (n + G - 1) / G;
+    per = (per + kGroupRun - 1) / kGroupRun * kGroupRun;
+    e0 = min(n, (int64_t)g * per);
+    e1 = min(n, e0 + per);
+}
+
+// Tile counts and rectangles (x0, x1, y0, y1 as two words) of entries
+// e .. e + kGroupRun - 1; counts at or past e1 read as zero.  Whole aligned
+// runs use 16-byte loads, all issued before any is used.
+__device__ __forceinline__ void load_run(const uint32_t* __restrict__ ntiles,
+                                         const uint2* __restrict__ rect, int64_t e, int64_t e1,
+                                         uint32_t (&n)[kGroupRun], uint2 (&rb)[kGroupRun])
+{
+    if (e + kGroupRun <= e1 && (reinterpret_cast<uintptr_t>(ntiles + e) & 15u) == 0u &&
+        (reinterpret_cast<uintptr_t>(rect + e) & 15u) == 0u) {
+        const uint4* pn = reinterpret_cast<const uint4*>(ntiles + e);
+        const uint4* pr = reinterpret_cast<const uint4*>(rect + e);
+        uint4 a[2], b[kGroupRun / 2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) a[r] = pn[r];
+#pragma unroll
+        for (int r = 0; r < kGroupRun / 2; ++r) b[r] = pr[r];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            n[4 * r + 0] = a[r].x;
+            n[4 * r + 1] = a[r].y;
+            n[4 * r + 2] = a[r].z;
+            n[4 * r + 3] = a[r].w;
+        }
+#pragma unroll
+        for (int r = 0; r < kGroupRun / 2; ++r) {
+            rb[2 * r] = make_uint2(b[r].x, b[r].y);
+            rb[2 * r + 1] = make_uint2(b[r].z, b[r].w);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kGroupRun; ++r) {
+            n[r] = e + r < e1 ? ntiles[e + r] : 0u;
+            rb[r] = n[r] != 0u ? rect[e + r] : make_uint2(0u, 0u);
+        }
+    }
+}
+
+// The first tile of entry e's rectangle, the rectangle's width in tiles and
+// the tile row pitch.
+struct TileWalk {
+    uint32_t first;
+    int nx, tw;
+};
+
+__device__ __forceinline__ TileWalk tile_walk(uint32_t e, uint2 rb, int tiles_x,
+                                              const ts_view* __restrict__ views, int64_t per_view)
+{
+    const int x0 = (int16_t)(rb.x & 0xffffu), x1 = (int16_t)(rb.x >> 16);
+    const int y0 = (int16_t)(rb.y & 0xffffu);
+    const int tx0 = x0 / kTile, nx = x1 / kTile - tx0 + 1, ty0 = y0 / kTile;
+    uint32_t toff = 0;
+    int tw = tiles_x;
+    if (views) {   // batched: entry = view * per_view + triangle
+        const ts_view& V = views[e / (uint64_t)per_view];
+        toff = V.tile_offset;
+        tw = (int)V.tiles_x;
+    }
+    return {toff + (uint32_t)(ty0 * tw + tx0), nx, tw};
+}
+
+// Calls f(tile) for the n tiles of a rectangle, row by row.
+template <class F>
+__device__ __forceinline__ void for_tiles(const TileWalk& tw, uint32_t n, F f)
+{
+    uint32_t row = tw.first;
+    int dx = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        f(row + (uint32_t)dx);
+        if (++dx == tw.nx) {
+            dx = 0;
+            row += (uint32_t)tw.tw;
+        }
+    }
+}
+
+// Per group: instances per tile (row g of hist, T wide), and the group's
+// instance and visible-entry totals in grp[g], grp[G + g].
+__global__ __launch_bounds__(kGroupThreads) void k_group_count(
+    const uint32_t* __restrict__ ntiles, const uint2* __restrict__ rect, int64_t N_host,
+    const uint32_t* __restrict__ d_n, int tiles_x, const ts_view* __restrict__ views,
+    int64_t per_view, int T, int G, uint32_t* __restrict__ hist, uint32_t* __restrict__ grp)
+{
+    extern __shared__ uint32_t s_h[];   // [T]
+    __shared__ uint32_t s_tmp[kGroupThreads / 64][2];
+    const int tid = threadIdx.x, g = xcd_group(G);
+    const int64_t N = d_n ? (int64_t)*d_n : N_host;
+    int64_t e0, e1;
+    group_span(N, G, g, e0, e1);
+    for (int t = tid; t < T; t += kGroupThreads) s_h[t] = 0u;
+    __syncthreads();
+    uint32_t m = 0, v = 0;
+    for (int64_t e = e0 + (int64_t)tid * kGroupRun; e < e1;
+         e += (int64_t)kGroupThreads * kGroupRun) {
+        uint32_t n[kGroupRun];
+        uint2 rb[kGroupRun];
+        load_run(ntiles, rect, e, e1, n, rb);
+#pragma unroll
+        for (int r = 0; r < kGroupRun; ++r) {
+            if (n[r] == 0u) continue;
+            m += n[r];
+            ++v;
+            const TileWalk tw = tile_walk((uint32_t)(e + r), rb[r], tiles_x, views, per_view);
+            for_tiles(tw, n[r], [&](uint32_t t) {
+                if (t < (uint32_t)T) atomicAdd(&s_h[t], 1u);
+            });
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        m += __shfl_xor(m, d, 64);
+        v += __shfl_xor(v, d, 64);
+    }
+    if ((tid & 63) == 0) {
+        s_tmp[tid >> 6][0] = m;
+        s_tmp[tid >> 6][1] = v;
+    }
+    __syncthreads();
+    uint32_t* row = hist + (int64_t)g * T;
+    for (int t = tid; t < T; t += kGroupThreads) row[t] = s_h[t];
+    if (tid < 2) {
+        uint32_t x = 0;
+        for (int j = 0; j < kGroupThreads / 64; ++j) x += s_tmp[j][tid];
+        grp[tid * G + g] = x;
+    }
+}
+
+// Column scan: hist[g][t] becomes the instances of tile t in groups before g;
+// tot[t] the tile's total.  64 tiles per workgroup; each of its 16 waves holds
+// a slice of up to 16 groups in registers.
+constexpr int kScanWaves = 16;
+constexpr int kScanSlice = kMaxGroups / kScanWaves;
+
+__global__ __launch_bounds__(64 * kScanWaves) void k_group_scan(uint32_t* __restrict__ hist, int T,
+                                                                int G, uint32_t* __restrict__ tot)
+{
+    __shared__ uint32_t s_sum[kScanWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + lane;
+    const int gq = (G + kScanWaves - 1) / kScanWaves, g0 = w * gq;
+    uint32_t x[kScanSlice];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanSlice; ++j) {
+        const int g = g0 + j;
+        x[j] = (j < gq && g < G && t < T) ? hist[(int64_t)g * T + t] : 0u;
+        sum += x[j];
+    }
+    s_sum[w][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, all = 0;
+#pragma unroll
+    for (int j = 0; j < kScanWaves; ++j) {
+        const uint32_t y = s_sum[j][lane];
+        run += j < w ? y : 0u;
+        all += y;
+    }
+#pragma unroll
+    for (int j = 0; j < kScanSlice; ++j) {
+        const int g = g0 + j;
+        if (j < gq && g < G && t < T) {
+            hist[(int64_t)g * T + t] = run;
+            run += x[j];
+        }
+    }
+    if (w == 0 && t < T) tot[t] = all;
+}
+
+// One workgroup: the totals (M, min(M, capacity), overflow, N_v), the ranges
+// of the T tiles from the exclusive scan of their totals (clamped to the
+// capacity; an empty tile's range is (0, 0)), and the longest-first order of
+// the first n tiles.  tot[t] is replaced by the tile's unclamped start.
+constexpr int kRangeSlice = kGroupTiles / kOrderThreads;   // tiles per thread
+static_assert(kRangeSlice * kOrderThreads == kGroupTiles, "whole slices");
+static_assert(kMaxGroups <= kOrderThreads, "one group total per thread");
+
+__global__ __launch_bounds__(kOrderThreads) void k_group_ranges(
+    uint32_t* __restrict__ tot, int T, const uint32_t* __restrict__ d_tiles,
+    const uint32_t* __restrict__ grp, int G, uint64_t capacity, uint32_t* __restrict__ ranges,
+    uint32_t* __restrict__ order, uint32_t* __restrict__ n_long, uint32_t* __restrict__ n_huge,
+    uint32_t* __restrict__ d_M, uint32_t* __restrict__ d_sortn, uint32_t* __restrict__ d_ovf,
+    uint32_t* __restrict__ d_Nv)
+{
+    extern __shared__ uint32_t s_len[];   // [T] clamped list lengths
+    __shared__ OrderSmem sm;
+    __shared__ uint32_t s_tmp[kOrderThreads / 64][2];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int t0 = tid * kRangeSlice;   // this thread's slice of tiles
+    uint32_t c[kRangeSlice];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kRangeSlice; ++r) {
+        c[r] = t0 + r < T ? tot[t0 + r] : 0u;
+        s += c[r];
+    }
+    uint32_t nv = tid < G ? grp[G + tid] : 0u;
+    uint32_t inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+        nv += __shfl_xor(nv, d, 64);
+    }
+    if (lane == 63) {
+        s_tmp[w][0] = inc;
+        s_tmp[w][1] = nv;
+    }
+    __syncthreads();
+    uint64_t start = inc - s, M = 0;
+    uint32_t NV = 0;
+    for (int j = 0; j < kOrderThreads / 64; ++j) {
+        start += j < w ? s_tmp[j][0] : 0u;
+        M += s_tmp[j][0];
+        NV += s_tmp[j][1];
+    }
+#pragma unroll
+    for (int r = 0; r < kRangeSlice; ++r) {
+        const int t = t0 + r;
+        if (t < T) {
+            const uint64_t end = start + c[r];
+            tot[t] = (uint32_t)start;
+            uint32_t a = (uint32_t)min(start, capacity), b = (uint32_t)min(end, capacity);
+            if (a == b) a = b = 0u;
+            ranges[2 * t] = a;
+            ranges[2 * t + 1] = b;
+            s_len[t] = b - a;
+            start = end;
+        }
+    }
+    if (tid == 0) {
+        *d_M = (uint32_t)M;
+        *d_sortn = (uint32_t)min(M, capacity);
+        *d_ovf = M > capacity ? 1u : 0u;
+        *d_Nv = NV;
+    }
+    __syncthreads();
+    const int n = d_tiles ? (int)min(*d_tiles, (uint32_t)T) : T;
+    order_tiles(n, [&](int t) { return s_len[t]; }, order, n_long, n_huge, sm);
+}
+
+// Per group: every instance goes to its tile's start + the group's offset in
+// the tile + the group's running count of the tile (LDS cursor); instances at
+// or past the capacity are dropped, as the clamped ranges say.
+__global__ __launch_bounds__(kGroupThreads) void k_group_place(
+    const uint32_t* __restrict__ ntiles, const uint2* __restrict__ rect, int64_t N_host,
+    const uint32_t* __restrict__ d_n, int tiles_x, const ts_view* __restrict__ views,
+    int64_t per_view, int T, int G, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ start, uint64_t capacity, uint32_t* __restrict__ vals)
+{
+    extern __shared__ uint32_t s_cur[];   // [T]
+    const int tid = threadIdx.x, g = xcd_group(G);
+    const uint32_t cap = capacity < 0xffffffffull ? (uint32_t)capacity : 0xffffffffu;
+    const int64_t N = d_n ? (int64_t)*d_n : N_host;
+    int64_t e0, e1;
+    group_span(N, G, g, e0, e1);
+    const uint32_t* row = hist + (int64_t)g * T;
+    for (int t = tid; t < T; t += kGroupThreads) s_cur[t] = start[t] + row[t];
+    __syncthreads();
+    for (int64_t e = e0 + (int64_t)tid * kGroupRun; e < e1;
+         e += (int64_t)kGroupThreads * kGroupRun) {
+        uint32_t n[kGroupRun];
+        uint2 rb[kGroupRun];
+        load_run(ntiles, rect, e, e1, n, rb);
+#pragma unroll
+        for (int r = 0; r < kGroupRun; ++r) {
+            if (n[r] == 0u) continue;
+            const uint32_t id = (uint32_t)(e + r);
+            for_tiles(tile_walk(id, rb[r], tiles_x, views, per_view), n[r], [&](uint32_t t) {
+                if (t < (uint32_t)T) {
+                    const uint32_t p = atomicAdd(&s_cur[t], 1u);
+                    if (p < cap) vals[p] = id;
+                }
+            });
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -597,22 +943,30 @@ __device__ uint32_t varying_bits(uint32_t a, uint32_t o, SortSmem& s)
 // L > 4 kWaveMax: each pass histograms the whole tile, then scatters it chunk by
 // chunk in order between two global buffers (k1/v1, k0/v0 at the tile's own
 // offsets); the last pass writes vals.  A single pass goes through k1/v1 and
-// is copied back, so no pass reads and writes the same buffer.
+// is copied back, so no pass reads and writes the same buffer.  A list that
+// is not in index order (by_index) is first sorted by the triangle index, in
+// passes over its varying bytes, so the depth passes see it in index order.
 __device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float* depth,
                                 uint32_t* vals, uint64_t* keys, uint32_t* k0, uint32_t* v0,
-                                uint32_t* k1, uint32_t* v1, SortSmem& sm)
+                                uint32_t* k1, uint32_t* v1, SortSmem& sm, bool by_index)
 {
     const int tid = threadIdx.x, w = tid >> 6;
-    uint32_t a = ~0u, o = 0u;
+    uint32_t a = ~0u, o = 0u, ai = ~0u, oi = 0u;
     for (int64_t j = tid; j < L; j += kBlock) {
-        const uint32_t k = __float_as_uint(depth[vals[s0 + j]]);
+        const uint32_t v = vals[s0 + j];
+        const uint32_t k = __float_as_uint(depth[v]);
         a &= k;
         o |= k;
+        ai &= v;
+        oi |= v;
     }
     const uint32_t diff = varying_bits(a, o, sm);
-    uint32_t pmask = 0;   // digits that need a pass
-    for (int p = 0; p < 4; ++p)
-        if (((diff >> (8 * p)) & 0xffu) != 0u) pmask |= 1u << p;
+    const uint32_t diff_i = by_index ? varying_bits(ai, oi, sm) : 0u;
+    uint32_t pmask = 0;   // digits that need a pass: bits 0-3 index bytes, 4-7 depth bytes
+    for (int p = 0; p < 4; ++p) {
+        if (((diff_i >> (8 * p)) & 0xffu) != 0u) pmask |= 1u << p;
+        if (((diff >> (8 * p)) & 0xffu) != 0u) pmask |= 1u << (p + 4);
+    }
     const int np = __popc(pmask);
     if (np == 0) {
         if (keys)
@@ -620,18 +974,19 @@ __device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float*
                 keys[s0 + j] = tile_key(t, __float_as_uint(depth[vals[s0 + j]]));
         return;
     }
-    const uint32_t* sk = nullptr;   // null: keys gathered from depth
+    const uint32_t* sk = nullptr;   // null: keys gathered from depth (or the index itself)
     const uint32_t* sv = vals + s0;
-    for (int p = 0, q = 0; p < 4; ++p) {
+    for (int p = 0, q = 0; p < 8; ++p) {
         if (((pmask >> p) & 1u) == 0u) continue;
-        const int shift = 8 * p;
+        const bool idx = p < 4;   // a pass over an index byte: the key is the value
+        const int shift = 8 * (p & 3);
         const bool last = q == np - 1 && np > 1;
         uint32_t* dk = last ? nullptr : ((q & 1) ? k0 : k1) + s0;
         uint32_t* dv = last ? vals + s0 : ((q & 1) ? v0 : v1) + s0;
         sm.base[tid] = 0u;
         __syncthreads();
         for (int64_t j = tid; j < L; j += kBlock) {
-            const uint32_t k = sk ? sk[j] : __float_as_uint(depth[sv[j]]);
+            const uint32_t k = idx ? sv[j] : sk ? sk[j] : __float_as_uint(depth[sv[j]]);
             atomicAdd(&sm.base[(k >> shift) & 0xffu], 1u);
         }
         __syncthreads();
@@ -651,7 +1006,7 @@ __device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float*
                 rank[r] = 0u;
                 if (j < n) {
                     val[r] = sv[c0 + j];
-                    key[r] = sk ? sk[c0 + j] : __float_as_uint(depth[val[r]]);
+                    key[r] = idx ? val[r] : sk ? sk[c0 + j] : __float_as_uint(depth[val[r]]);
                 }
             }
             const uint32_t cnt = rank_chunk(key, n, shift, sm, rank);
@@ -661,23 +1016,26 @@ __device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float*
                 if (j < n) {
                     const uint32_t d = (key[r] >> shift) & 0xffu;
                     const uint32_t pos = sm.base[d] + sm.cnt[r * 4 + w][d] + rank[r];
-                    if (dk) dk[pos] = key[r];
+                    if (dk && !idx) dk[pos] = key[r];
                     dv[pos] = val[r];
-                    if (last && keys) keys[s0 + pos] = tile_key(t, key[r]);
+                    if (last && keys)
+                        keys[s0 + pos] =
+                            tile_key(t, idx ? __float_as_uint(depth[val[r]]) : key[r]);
                 }
             }
             __syncthreads();
             sm.base[tid] += cnt;
             __syncthreads();
         }
-        sk = dk;
+        sk = idx ? nullptr : dk;
         sv = dv;
         ++q;
     }
     if (np == 1)
         for (int64_t j = tid; j < L; j += kBlock) {
-            vals[s0 + j] = v1[s0 + j];
-            if (keys) keys[s0 + j] = tile_key(t, k1[s0 + j]);
+            const uint32_t v = v1[s0 + j];
+            vals[s0 + j] = v;
+            if (keys) keys[s0 + j] = tile_key(t, __float_as_uint(depth[v]));
         }
 }
 
@@ -863,8 +1221,9 @@ __device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __re
 // than kWaveMax and get a whole workgroup each (four wave-level sorts of a
 // quarter each and a merge in LDS up to 4 kWaveMax entries, global ping-pong
 // or the segmented sort beyond); every later workgroup gives each of its four
-// waves one tile.  The instances of a tile arrive in index order; they leave
-// in (depth, index) order, with their 64-bit keys when keys is set.
+// waves one tile.  The instances of a tile arrive in index order, or in any
+// order when `unordered` is set; they leave in (depth, index) order, with
+// their 64-bit keys when keys is set.
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ n_long,
@@ -876,7 +1235,8 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
                                                    uint32_t* __restrict__ k0,
                                                    uint32_t* __restrict__ v0,
                                                    uint32_t* __restrict__ k1,
-                                                   uint32_t* __restrict__ v1, int segmented)
+                                                   uint32_t* __restrict__ v1, int segmented,
+                                                   int unordered)
 {
     __shared__ TileSortSmem sm;
     const uint32_t n = d_tiles ? min(*d_tiles, (uint32_t)num_tiles) : (uint32_t)num_tiles;
@@ -893,7 +1253,8 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     const uint32_t s0 = ranges[2 * t];
     const int64_t L = (int64_t)ranges[2 * t + 1] - (int64_t)s0;
     if (blockIdx.x < nl && L > kHugeLen) {   // the whole workgroup, in global memory
-        if (!segmented) sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk);
+        if (!segmented)
+            sort_tile_large(L, s0, t, depth, vals, keys, k0, v0, k1, v1, sm.blk, unordered != 0);
         return;   // else the segmented sort below takes the tile
     }
     if (blockIdx.x < nl) {   // the whole workgroup: four quarters and a merge
@@ -1210,6 +1571,45 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     uint32_t* d_Nv = out.d_count + 1;   // [1] N_v
     uint32_t* d_ovf = out.d_count + 2;  // [2] overflow
     uint32_t* d_sortn = ws.ctl;         // min(M, capacity)
+    const bool seg = (out.flags & TS_BINS_SEGMENTED_SORT) != 0u;
+    uint32_t* order = out.order ? out.order : ws.torder;
+    uint32_t* n_long = ws.ctl + 1;
+
+    if (!seg && num_tiles > 0 && num_tiles <= kGroupTiles) {
+        // 1'. group tile counts, column scan, ranges and order, placement
+        const int64_t want = (N + kGroupEntries - 1) / kGroupEntries;
+        const int G = want < 1 ? 1 : want > kMaxGroups ? kMaxGroups : (int)want;
+        const size_t lds = 4 * (size_t)num_tiles;
+        const uint2* r4 = reinterpret_cast<const uint2*>(rect);
+        hipLaunchKernelGGL(k_group_count, dim3((unsigned)G), dim3(kGroupThreads), lds, stream,
+                           ntiles, r4, N, d_n, tiles_x, views, per_view, num_tiles, G, ws.hist,
+                           ws.blk);
+        hipLaunchKernelGGL(k_group_scan, dim3((unsigned)((num_tiles + 63) / 64)),
+                           dim3(64 * kScanWaves), 0,
+                           stream, ws.hist, num_tiles, G, ws.hl);
+        hipLaunchKernelGGL(k_group_ranges, dim3(1), dim3(kOrderThreads), lds, stream,
+                           ws.hl, num_tiles, d_tiles, (const uint32_t*)ws.blk, G,
+                           out.capacity, out.ranges, order, n_long, out.d_count + 3, d_M, d_sortn,
+                           d_ovf, d_Nv);
+        hipLaunchKernelGGL(k_group_place, dim3((unsigned)G), dim3(kGroupThreads), lds, stream,
+                           ntiles, r4, N, d_n, tiles_x, views, per_view, num_tiles, G,
+                           (const uint32_t*)ws.hist, (const uint32_t*)ws.hl, out.capacity,
+                           out.vals);
+        // 4. depth order inside every tile
+        hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)num_tiles), dim3(kBlock), 0, stream,
+                           out.ranges, (const uint32_t*)order, (const uint32_t*)n_long, num_tiles,
+                           d_tiles, depth, out.vals, out.keys, ws.tk[0], ws.tv[0], ws.tk[1],
+                           ws.tv[1], 0, 1);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess || !h_count) return err;
+        err = hipMemcpyAsync(h_count, out.d_count, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             stream);
+        if (err != hipSuccess) return err;
+        err = hipStreamSynchronize(stream);
+        if (err != hipSuccess) return err;
+        *overflow = (uint64_t)h_count[0] > out.capacity;
+        return hipSuccess;
+    }
 
     // 1. tile counts of the N (or *d_n) entries in index order; ranges cleared
     hipLaunchKernelGGL(k_count, dim3((unsigned)nbN), dim3(kBlock), 0, stream, ntiles, N, d_n,
@@ -1243,16 +1643,13 @@ hipError_t run_bin_sort(const uint32_t* ntiles, const float* depth, const int16_
     if (m_max > 0)
         hipLaunchKernelGGL(k_ranges, dim3((unsigned)((m_max + 255) / 256)), dim3(256), 0, stream,
                            ws.tfin, d_sortn, out.ranges);
-    uint32_t* order = out.order ? out.order : ws.torder;
-    uint32_t* n_long = ws.ctl + 1;
     launch_tile_order(out.ranges, num_tiles, d_tiles, order, stream, n_long, out.d_count + 3);
     // 4. depth order inside every tile
-    const bool seg = (out.flags & TS_BINS_SEGMENTED_SORT) != 0u;
     if (m_max > 0 && num_tiles > 0)
         hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)num_tiles), dim3(kBlock), 0, stream,
                            out.ranges, (const uint32_t*)order, (const uint32_t*)n_long, num_tiles,
                            d_tiles, depth, out.vals, out.keys, ws.tk[0], ws.tv[0], ws.tk[1],
-                           ws.tv[1], seg ? 1 : 0);
+                           ws.tv[1], seg ? 1 : 0, 0);
     if (seg && m_max > 0 && num_tiles > 0) {
         // 4b. the huge tiles, spread over many workgroups: four stable passes
         hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(kOrderThreads), 0, stream, out.ranges,
