@@ -665,6 +665,49 @@ __device__ __forceinline__ void for_tiles(const TileWalk& tw, uint32_t n, F f)
     }
 }
 
+// Calls f(tile, entry) for every instance of the run's entries e .. e + 7:
+// entries of up to kLaneTiles tiles by their own lane, larger ones (a
+// triangle can cover hundreds of tiles) one at a time by all active lanes of
+// the wave, so no lane walks a long rectangle alone.
+constexpr uint32_t kLaneTiles = 8;
+
+template <class F>
+__device__ __forceinline__ void for_run_tiles(int64_t e, const uint32_t (&n)[kGroupRun],
+                                              const uint2 (&rb)[kGroupRun], int tiles_x,
+                                              const ts_view* __restrict__ views, int64_t per_view,
+                                              F f)
+{
+#pragma unroll
+    for (int r = 0; r < kGroupRun; ++r) {
+        if (n[r] != 0u && n[r] <= kLaneTiles) {
+            const uint32_t id = (uint32_t)(e + r);
+            for_tiles(tile_walk(id, rb[r], tiles_x, views, per_view), n[r],
+                      [&](uint32_t t) { f(t, id); });
+        }
+    }
+    const uint64_t act = __ballot(1);
+    const uint32_t nact = (uint32_t)__popcll(act);
+    const int lane = threadIdx.x & 63;
+    const uint32_t rank = (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int r = 0; r < kGroupRun; ++r) {
+        uint64_t want = __ballot(n[r] > kLaneTiles);
+        while (want != 0ull) {   // the same for all active lanes
+            const int src = (int)__builtin_ctzll(want);
+            want &= want - 1ull;
+            const uint32_t ns = (uint32_t)__shfl((int)n[r], src, 64);
+            const uint32_t id = (uint32_t)__shfl((int)(uint32_t)(e + r), src, 64);
+            const uint2 rs = make_uint2((uint32_t)__shfl((int)rb[r].x, src, 64),
+                                        (uint32_t)__shfl((int)rb[r].y, src, 64));
+            const TileWalk tw = tile_walk(id, rs, tiles_x, views, per_view);
+            for (uint32_t k = rank; k < ns; k += nact) {
+                const uint32_t dy = k / (uint32_t)tw.nx, dx = k - dy * (uint32_t)tw.nx;
+                f(tw.first + dy * (uint32_t)tw.tw + dx, id);
+            }
+        }
+    }
+}
+
 // Per group: instances per tile (row g of hist, T wide), and the group's
 // instance and visible-entry totals in grp[g], grp[G + g].
 __global__ __launch_bounds__(kGroupThreads) void k_group_count(
@@ -688,14 +731,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_count(
         load_run(ntiles, rect, e, e1, n, rb);
 #pragma unroll
         for (int r = 0; r < kGroupRun; ++r) {
-            if (n[r] == 0u) continue;
             m += n[r];
-            ++v;
-            const TileWalk tw = tile_walk((uint32_t)(e + r), rb[r], tiles_x, views, per_view);
-            for_tiles(tw, n[r], [&](uint32_t t) {
-                if (t < (uint32_t)T) atomicAdd(&s_h[t], 1u);
-            });
+            v += n[r] != 0u ? 1u : 0u;
         }
+        for_run_tiles(e, n, rb, tiles_x, views, per_view, [&](uint32_t t, uint32_t) {
+            if (t < (uint32_t)T) atomicAdd(&s_h[t], 1u);
+        });
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
@@ -852,17 +893,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place(
         uint32_t n[kGroupRun];
         uint2 rb[kGroupRun];
         load_run(ntiles, rect, e, e1, n, rb);
-#pragma unroll
-        for (int r = 0; r < kGroupRun; ++r) {
-            if (n[r] == 0u) continue;
-            const uint32_t id = (uint32_t)(e + r);
-            for_tiles(tile_walk(id, rb[r], tiles_x, views, per_view), n[r], [&](uint32_t t) {
-                if (t < (uint32_t)T) {
-                    const uint32_t p = atomicAdd(&s_cur[t], 1u);
-                    if (p < cap) vals[p] = id;
-                }
-            });
-        }
+        for_run_tiles(e, n, rb, tiles_x, views, per_view, [&](uint32_t t, uint32_t id) {
+            if (t < (uint32_t)T) {
+                const uint32_t p = atomicAdd(&s_cur[t], 1u);
+                if (p < cap) vals[p] = id;
+            }
+        });
     }
 }
 
