@@ -20,7 +20,7 @@
 //      ceil(log2 tiles / 8) passes over M with the bits split evenly between
 //      them; inside a tile the triangles are still in index order
 // Then:
-//   4. each tile's entries are put in (depth key, index) order: up to 1024
+//   4. each tile's entries are put in (depth key, index) order: up to 256
 //      entries by one wave, a bitonic network over 64-bit (depth, index)
 //      keys held in registers; up to 4096 by four waves (a quarter each) and
 //      a merge in LDS; beyond, a stable radix sort by depth of the run in
@@ -456,10 +456,14 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t x, hipStream_t stream)
 // launch.  One workgroup; ctl (optional) holds the number of tiles.
 constexpr int kLenBuckets = 2048;
 
-// n_long (optional) receives the number of tiles longer than kWaveMax: they
-// lead the order, since kWaveMax < kLenBuckets - 1.
-constexpr int kWaveMax = 1024;   // longest list one wave sorts on its own
-static_assert(kWaveMax < kLenBuckets - 1, "long tiles must lead the order");
+// n_long (optional) receives the number of tiles longer than kWaveSortMax:
+// they lead the order, since kWaveSortMax < kLenBuckets - 1.
+constexpr int kWaveMax = 1024;   // longest list one wave's register network holds
+// Longer lists get a whole workgroup (four quarter sorts and a merge): the
+// quarters' shorter compare-exchange chains finish sooner than one wave's.
+constexpr int kWaveSortMax = 256;
+static_assert(kWaveSortMax <= kWaveMax && kWaveSortMax < kLenBuckets - 1,
+              "long tiles must lead the order");
 
 constexpr int kOrderThreads = 1024;
 
@@ -494,7 +498,7 @@ __device__ void order_tiles(int n, Len len_of, uint32_t* __restrict__ order,
     };
     for (int t = tid; t < n; t += kOrderThreads) {
         atomicAdd(&h[key(t)], 1u);
-        if (len_of(t) > (uint32_t)kWaveMax) atomicAdd(&s_long, 1u);
+        if (len_of(t) > (uint32_t)kWaveSortMax) atomicAdd(&s_long, 1u);
         if (len_of(t) > (uint32_t)kHugeLen) atomicAdd(&s_huge, 1u);
     }
     __syncthreads();
@@ -905,9 +909,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place(
 // ---------------------------------------------------------------------------
 // 4. per-tile depth order
 // ---------------------------------------------------------------------------
-struct SortSmem {
-    uint32_t key[kChunk];
-    uint32_t val[kChunk];
+struct SortSmem {   // the huge-tile block sort's digit counters
     uint16_t cnt[kItems * 4][kRadix];
     uint32_t base[kRadix];
     uint32_t tmp[4];
@@ -1075,12 +1077,14 @@ __device__ void sort_tile_large(int64_t L, uint32_t s0, uint32_t t, const float*
         }
 }
 
-// ---- one wave per tile (L <= kWaveMax) ------------------------------------
+// ---- one wave per tile (L <= kWaveSortMax), or per quarter of a longer one --
 
+// 32 KB: five workgroups fit in a CU's 160 KB of LDS
 union TileSortSmem {
     SortSmem blk;
     uint64_t kv[(kBlock / 64) * kWaveMax];   // a long tile's four sorted quarters, merged in place
 };
+static_assert(sizeof(TileSortSmem) <= 32768, "five workgroups per CU");
 
 
 // Bitonic sort of one tile's L <= 64 K entries by one wave, K entries per
@@ -1254,7 +1258,7 @@ __device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __re
 }
 
 // Tiles taken in `order` (longest first); the first n_long of them are longer
-// than kWaveMax and get a whole workgroup each (four wave-level sorts of a
+// than kWaveSortMax and get a whole workgroup each (four wave-level sorts of a
 // quarter each and a merge in LDS up to 4 kWaveMax entries, global ping-pong
 // or the segmented sort beyond); every later workgroup gives each of its four
 // waves one tile.  The instances of a tile arrive in index order, or in any
@@ -1294,7 +1298,9 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
         return;   // else the segmented sort below takes the tile
     }
     if (blockIdx.x < nl) {   // the whole workgroup: four quarters and a merge
-        if (L <= 4 * 512) sort_long_tile<8>((int)L, s0, t, depth, vals, keys, sm.kv);
+        if (L <= 4 * 128) sort_long_tile<2>((int)L, s0, t, depth, vals, keys, sm.kv);
+        else if (L <= 4 * 256) sort_long_tile<4>((int)L, s0, t, depth, vals, keys, sm.kv);
+        else if (L <= 4 * 512) sort_long_tile<8>((int)L, s0, t, depth, vals, keys, sm.kv);
         else sort_long_tile<16>((int)L, s0, t, depth, vals, keys, sm.kv);
         return;
     }
@@ -1302,7 +1308,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     if (L == 1) {
         if (keys && (threadIdx.x & 63) == 0)
             keys[s0] = tile_key(t, __float_as_uint(depth[vals[s0]]));
-    } else if (L > 1 && L <= kWaveMax) {
+    } else if (L > 1 && L <= kWaveSortMax) {
         sort_tile_bitonic((int)L, s0, t, depth, vals, keys);
     }
 }
