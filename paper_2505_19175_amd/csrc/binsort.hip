@@ -1208,11 +1208,58 @@ __device__ void sort_tile_bitonic(int L, uint32_t s0, uint32_t t, const float* _
     else bitonic_tile<16>(L, s0, t, depth, vals, keys);
 }
 
+// The non-flip steps of strides STRIDE, STRIDE / 2, ..., 1 on a wave's 64 K
+// keys (layout as in bitonic_stages): the end of a merge whose first steps
+// crossed waves.
+template <int K, int STRIDE>
+__device__ __forceinline__ void half_clean(uint64_t (&x)[K], int lane)
+{
+    if constexpr (STRIDE < K) {   // both elements in this lane
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int q = r ^ STRIDE;
+            if (r < q) {
+                const uint64_t a = x[r], b = x[q];
+                const bool lt = a < b;
+                x[r] = lt ? a : b;
+                x[q] = lt ? b : a;
+            }
+        }
+    } else {
+        constexpr int LD = STRIDE / K;
+        const bool lower = (lane & LD) == 0;
+        uint64_t y[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) y[r] = shfl_xor64<LD>(x[r]);
+#pragma unroll
+        for (int r = 0; r < K; ++r) x[r] = (lower == (x[r] < y[r])) ? x[r] : y[r];
+    }
+    if constexpr (STRIDE > 1) half_clean<K, STRIDE / 2>(x, lane);
+}
+
+// One merge step over the workgroup's N keys in LDS: the pairs (e, e ^ (S-1))
+// of every block of S (flip) or (e, e + S) (stride S), smaller key first.
+template <bool FLIP>
+__device__ __forceinline__ void lds_step(uint64_t* __restrict__ kv, int S, int N)
+{
+    const int half = FLIP ? S >> 1 : S;
+    for (int p = threadIdx.x; p < N / 2; p += kBlock) {
+        const int off = p & (half - 1), blk = p - off;
+        const int i = 2 * blk + off;
+        const int j = FLIP ? 2 * blk + S - 1 - off : i + S;
+        const uint64_t a = kv[i], b = kv[j];
+        if (b < a) {
+            kv[i] = b;
+            kv[j] = a;
+        }
+    }
+}
+
 // A long tile: wave w sorts quarter w (entries w * Qa .. of the tile, Qa =
-// ceil(L / 4)) with the register network into kv[w * 64 K ..], every one of
-// its 64 K slots written (past the quarter, the largest key); then the
-// workgroup merges the four ascending runs in LDS with the last two levels of
-// the same direction-free network, and writes the first L keys out.
+// ceil(L / 4)) with the register network, padded to Q = 64 K keys with the
+// largest one; the last two levels of the same direction-free network merge
+// the four runs.  Only their steps whose pairs cross waves (each level's
+// first, and stride Q of the last) go through LDS; the rest run in registers.
 template <int K>
 __device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __restrict__ depth,
                                uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
@@ -1224,36 +1271,34 @@ __device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __re
     const int q0 = w * Qa;
     uint64_t x[K];
     wave_sorted<K>(max(0, min(Qa, L - q0)), s0 + (uint32_t)q0, depth, vals, x);
+    uint64_t* mine = kv + w * Q + lane * K;
+    // level 2Q: the flip pairs waves 0-1 and 2-3, then strides Q/2 .. 1
 #pragma unroll
-    for (int r = 0; r < K; ++r) kv[w * Q + lane * K + r] = x[r];
+    for (int r = 0; r < K; ++r) mine[r] = x[r];
     __syncthreads();
-    for (int size = 2 * Q; size <= N; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const bool flip = stride == (size >> 1);
-            for (int p = tid; p < N / 2; p += kBlock) {
-                int i, j;
-                if (flip) {   // e with e ^ (size - 1): the lower half of each block
-                    const int off = p & (stride - 1), blk = p - off;   // stride = size / 2
-                    i = 2 * blk + off;
-                    j = 2 * blk + size - 1 - off;
-                } else {
-                    const int off = p & (stride - 1);
-                    i = 2 * (p - off) + off;
-                    j = i + stride;
-                }
-                const uint64_t a = kv[i], b = kv[j];
-                if (b < a) {
-                    kv[i] = b;
-                    kv[j] = a;
-                }
-            }
-            __syncthreads();
+    lds_step<true>(kv, 2 * Q, N);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < K; ++r) x[r] = mine[r];
+    half_clean<K, Q / 2>(x, lane);
+    // level 4Q: the flip and stride Q cross waves, then strides Q/2 .. 1
+#pragma unroll
+    for (int r = 0; r < K; ++r) mine[r] = x[r];
+    __syncthreads();
+    lds_step<true>(kv, 4 * Q, N);
+    __syncthreads();
+    lds_step<false>(kv, Q, N);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < K; ++r) x[r] = mine[r];
+    half_clean<K, Q / 2>(x, lane);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int e = w * Q + lane * K + r;
+        if (e < L) {
+            vals[s0 + e] = (uint32_t)x[r];
+            if (keys) keys[s0 + e] = tile_key(t, (uint32_t)(x[r] >> 32));
         }
-    }
-    for (int e = tid; e < L; e += kBlock) {
-        const uint64_t y = kv[e];
-        vals[s0 + e] = (uint32_t)y;
-        if (keys) keys[s0 + e] = tile_key(t, (uint32_t)(y >> 32));
     }
 }
 
