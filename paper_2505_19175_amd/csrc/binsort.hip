@@ -20,7 +20,7 @@
 //      ceil(log2 tiles / 8) passes over M with the bits split evenly between
 //      them; inside a tile the triangles are still in index order
 // Then:
-//   4. each tile's entries are put in (depth key, index) order: up to 256
+//   4. each tile's entries are put in (depth key, index) order: up to 128
 //      entries by one wave, a bitonic network over 64-bit (depth, index)
 //      keys held in registers; up to 4096 by four waves (a quarter each) and
 //      a merge in LDS; beyond, a stable radix sort by depth of the run in
@@ -461,7 +461,7 @@ constexpr int kLenBuckets = 2048;
 constexpr int kWaveMax = 1024;   // longest list one wave's register network holds
 // Longer lists get a whole workgroup (four quarter sorts and a merge): the
 // quarters' shorter compare-exchange chains finish sooner than one wave's.
-constexpr int kWaveSortMax = 256;
+constexpr int kWaveSortMax = 128;
 static_assert(kWaveSortMax <= kWaveMax && kWaveSortMax < kLenBuckets - 1,
               "long tiles must lead the order");
 
@@ -1237,9 +1237,18 @@ __device__ __forceinline__ void half_clean(uint64_t (&x)[K], int lane)
     if constexpr (STRIDE > 1) half_clean<K, STRIDE / 2>(x, lane);
 }
 
+// LDS slot of key e of a long tile: inside each run of K keys (one lane's)
+// the slot is XORed with the lane's low bits, so the lanes of a wave storing
+// their r-th keys hit different banks.
+template <int K>
+__device__ __forceinline__ int kv_slot(int e)
+{
+    return e ^ ((e / K) & (K - 1));
+}
+
 // One merge step over the workgroup's N keys in LDS: the pairs (e, e ^ (S-1))
 // of every block of S (flip) or (e, e + S) (stride S), smaller key first.
-template <bool FLIP>
+template <int K, bool FLIP>
 __device__ __forceinline__ void lds_step(uint64_t* __restrict__ kv, int S, int N)
 {
     const int half = FLIP ? S >> 1 : S;
@@ -1247,10 +1256,11 @@ __device__ __forceinline__ void lds_step(uint64_t* __restrict__ kv, int S, int N
         const int off = p & (half - 1), blk = p - off;
         const int i = 2 * blk + off;
         const int j = FLIP ? 2 * blk + S - 1 - off : i + S;
-        const uint64_t a = kv[i], b = kv[j];
+        const int si = kv_slot<K>(i), sj = kv_slot<K>(j);
+        const uint64_t a = kv[si], b = kv[sj];
         if (b < a) {
-            kv[i] = b;
-            kv[j] = a;
+            kv[si] = b;
+            kv[sj] = a;
         }
     }
 }
@@ -1271,26 +1281,27 @@ __device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __re
     const int q0 = w * Qa;
     uint64_t x[K];
     wave_sorted<K>(max(0, min(Qa, L - q0)), s0 + (uint32_t)q0, depth, vals, x);
-    uint64_t* mine = kv + w * Q + lane * K;
+    uint64_t* mine = kv + w * Q + lane * K;   // key r of this lane at mine[r ^ sw]
+    const int sw = lane & (K - 1);
     // level 2Q: the flip pairs waves 0-1 and 2-3, then strides Q/2 .. 1
 #pragma unroll
-    for (int r = 0; r < K; ++r) mine[r] = x[r];
+    for (int r = 0; r < K; ++r) mine[r ^ sw] = x[r];
     __syncthreads();
-    lds_step<true>(kv, 2 * Q, N);
+    lds_step<K, true>(kv, 2 * Q, N);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < K; ++r) x[r] = mine[r];
+    for (int r = 0; r < K; ++r) x[r] = mine[r ^ sw];
     half_clean<K, Q / 2>(x, lane);
     // level 4Q: the flip and stride Q cross waves, then strides Q/2 .. 1
 #pragma unroll
-    for (int r = 0; r < K; ++r) mine[r] = x[r];
+    for (int r = 0; r < K; ++r) mine[r ^ sw] = x[r];
     __syncthreads();
-    lds_step<true>(kv, 4 * Q, N);
+    lds_step<K, true>(kv, 4 * Q, N);
     __syncthreads();
-    lds_step<false>(kv, Q, N);
+    lds_step<K, false>(kv, Q, N);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < K; ++r) x[r] = mine[r];
+    for (int r = 0; r < K; ++r) x[r] = mine[r ^ sw];
     half_clean<K, Q / 2>(x, lane);
 #pragma unroll
     for (int r = 0; r < K; ++r) {
@@ -1343,7 +1354,8 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
         return;   // else the segmented sort below takes the tile
     }
     if (blockIdx.x < nl) {   // the whole workgroup: four quarters and a merge
-        if (L <= 4 * 128) sort_long_tile<2>((int)L, s0, t, depth, vals, keys, sm.kv);
+        if (L <= 4 * 64) sort_long_tile<1>((int)L, s0, t, depth, vals, keys, sm.kv);
+        else if (L <= 4 * 128) sort_long_tile<2>((int)L, s0, t, depth, vals, keys, sm.kv);
         else if (L <= 4 * 256) sort_long_tile<4>((int)L, s0, t, depth, vals, keys, sm.kv);
         else if (L <= 4 * 512) sort_long_tile<8>((int)L, s0, t, depth, vals, keys, sm.kv);
         else sort_long_tile<16>((int)L, s0, t, depth, vals, keys, sm.kv);
