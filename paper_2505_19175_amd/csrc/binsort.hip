@@ -1315,8 +1315,8 @@ __device__ void sort_long_tile(int L, uint32_t s0, uint32_t t, const float* __re
 
 // Tiles taken in `order` (longest first); the first n_long of them are longer
 // than kWaveSortMax and get a whole workgroup each (four wave-level sorts of a
-// quarter each and a merge in LDS up to 4 kWaveMax entries, global ping-pong
-// or the segmented sort beyond); every later workgroup gives each of its four
+// quarter each and a two-level merge up to 4 kWaveMax entries, global
+// ping-pong or the segmented sort beyond); every later workgroup gives each of its four
 // waves one tile.  The instances of a tile arrive in index order, or in any
 // order when `unordered` is set; they leave in (depth, index) order, with
 // their 64-bit keys when keys is set.
